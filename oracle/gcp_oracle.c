@@ -1,0 +1,372 @@
+/*
+ * gcp_oracle.c -- plain, slow, serial FP64 CPU oracle for the GCP sampled
+ * stochastic gradient (Myers & Phipps, "Synchronous and Asynchronous
+ * Parallelism Approaches for Generalized Canonical Polyadic Tensor
+ * Decomposition with GenTen", arXiv 2605.20353).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or helper with the HIP library: it has its own
+ * Philox4x64-10, its own membership search (lexicographically sorted
+ * coordinate tuples + binary search, the O(log N) search of Sec. 3.1.1) and
+ * its own serial MTTKRP (the "serial" strategy of Sec. 3.1.2).  Everything is
+ * computed in double precision.
+ *
+ * Conventions (0-based indices; the paper writes 1-based ranges):
+ *   - A Kruskal model is ONE contiguous array of sum_k I_k rows of R values,
+ *     row-major, mode 0's rows first (the single contiguous factor array of
+ *     Sec. 3.1.3).  rowoff[k] = sum_{j<k} I_j.
+ *   - Sample lists are (coords [n x d] int64 row-major, x [n], w [n]).
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based RNG: Philox4x64 with 10 rounds, as defined by Salmon,      */
+/* Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3"     */
+/* (SC'11).  The paper leaves the RNG unspecified; this is the reading.     */
+/* ------------------------------------------------------------------------ */
+
+/* Round multipliers and Weyl key increments published with Philox4x64. */
+#define ORA_PHILOX_M0 0xD2E7470EE14C6C93ULL
+#define ORA_PHILOX_M1 0xCA5A826395121157ULL
+#define ORA_PHILOX_W0 0x9E3779B97F4A7C15ULL
+#define ORA_PHILOX_W1 0xBB67AE8584CAA73BULL
+
+void ora_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {           /* key schedule: bump between rounds */
+            k0 += ORA_PHILOX_W0;
+            k1 += ORA_PHILOX_W1;
+        }
+        u128 p0 = (u128)ORA_PHILOX_M0 * (u128)x0;
+        u128 p1 = (u128)ORA_PHILOX_M1 * (u128)x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t y0 = hi1 ^ x1 ^ k0;
+        uint64_t y1 = lo1;
+        uint64_t y2 = hi0 ^ x3 ^ k1;
+        uint64_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Exact map of a 64-bit uniform word u onto [0, n): floor(u * n / 2^64). */
+uint64_t ora_range(uint64_t u, uint64_t n)
+{
+    return (uint64_t)(((u128)u * (u128)n) >> 64);
+}
+
+/* Stream tags carried in the third counter word (low 8 bits); the rejection
+ * attempt number sits above them. */
+enum { ORA_STREAM_NONZERO = 0, ORA_STREAM_ZERO = 1, ORA_STREAM_UNIFORM = 2 };
+
+/* Draw the d coordinates of one candidate cell for sample s, attempt t. */
+static void ora_draw_cell(int d, const int64_t* dims, uint64_t seed, uint64_t client,
+                          uint64_t s, uint64_t step, uint64_t stream, uint64_t attempt,
+                          int64_t* idx)
+{
+    uint64_t key[2] = {seed, client};
+    for (int blk = 0; blk * 4 < d; ++blk) {
+        uint64_t ctr[4] = {s, step, stream | (attempt << 8), (uint64_t)blk};
+        uint64_t out[4];
+        ora_philox4x64_10(ctr, key, out);
+        for (int j = 0; j < 4 && blk * 4 + j < d; ++j) {
+            int k = blk * 4 + j;
+            idx[k] = (int64_t)ora_range(out[j], (uint64_t)dims[k]);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sparse tensor in coordinate (COO) format with a lexicographically sorted */
+/* index for O(log N) membership search (Sec. 3.1.1).                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int d;
+    int64_t dims[8];
+    int64_t nnz;
+    const int64_t* coords; /* borrowed, nnz x d */
+    const double* vals;    /* borrowed, nnz */
+    int64_t* order;        /* owned: positions sorted by coordinate tuple */
+} ora_tensor;
+
+static int ora_cmp_tuple(const int64_t* a, const int64_t* b, int d)
+{
+    for (int k = 0; k < d; ++k) {
+        if (a[k] < b[k]) return -1;
+        if (a[k] > b[k]) return 1;
+    }
+    return 0;
+}
+
+static int ora_cmp_positions(const void* pa, const void* pb, void* arg)
+{
+    const ora_tensor* t = (const ora_tensor*)arg;
+    int64_t a = *(const int64_t*)pa, b = *(const int64_t*)pb;
+    return ora_cmp_tuple(t->coords + a * t->d, t->coords + b * t->d, t->d);
+}
+
+/* Status codes shared by the oracle entry points. */
+enum { ORA_OK = 0, ORA_ERR_ARG = -1, ORA_ERR_SAMPLING = -4 };
+
+/* Builds the sorted index.  *status = ORA_ERR_ARG on a coordinate outside the
+ * dims or on a repeated coordinate tuple (the nonzero list must be a set). */
+ora_tensor* ora_tensor_new(int d, const int64_t* dims, int64_t nnz, const int64_t* coords,
+                           const double* vals, int* status)
+{
+    *status = ORA_ERR_ARG;
+    if (d < 1 || d > 8 || nnz < 0) return NULL;
+    ora_tensor* t = (ora_tensor*)calloc(1, sizeof(ora_tensor));
+    t->d = d;
+    for (int k = 0; k < d; ++k) t->dims[k] = dims[k];
+    t->nnz = nnz;
+    t->coords = coords;
+    t->vals = vals;
+    t->order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+    for (int64_t j = 0; j < nnz; ++j) {
+        for (int k = 0; k < d; ++k) {
+            int64_t c = coords[j * d + k];
+            if (c < 0 || c >= dims[k]) { free(t->order); free(t); return NULL; }
+        }
+        t->order[j] = j;
+    }
+    qsort_r(t->order, (size_t)nnz, sizeof(int64_t), ora_cmp_positions, t);
+    for (int64_t j = 1; j < nnz; ++j) {
+        if (ora_cmp_tuple(coords + t->order[j - 1] * d, coords + t->order[j] * d, d) == 0) {
+            free(t->order); free(t); return NULL;
+        }
+    }
+    *status = ORA_OK;
+    return t;
+}
+
+void ora_tensor_free(ora_tensor* t)
+{
+    if (!t) return;
+    free(t->order);
+    free(t);
+}
+
+/* Binary search: position of the nonzero with coordinates idx, or -1. */
+int64_t ora_find(const ora_tensor* t, const int64_t* idx)
+{
+    int64_t lo = 0, hi = t->nnz; /* search in order[lo, hi) */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        int c = ora_cmp_tuple(t->coords + t->order[mid] * t->d, idx, t->d);
+        if (c == 0) return t->order[mid];
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+static double ora_cell_count(int d, const int64_t* dims)
+{
+    int64_t M = 1;
+    for (int k = 0; k < d; ++k) M *= dims[k];
+    return (double)M;
+}
+
+static int64_t ora_cell_count_i(int d, const int64_t* dims)
+{
+    int64_t M = 1;
+    for (int k = 0; k < d; ++k) M *= dims[k];
+    return M;
+}
+
+/* Stratified sampling (Sec. 3.1.1): p nonzeros drawn uniformly with
+ * replacement from the N stored entries, weight N/p; then q zeros, each the
+ * first candidate cell (uniform over all M cells) that is not a stored
+ * nonzero, weight (M-N)/q.  With semi != 0 the search is skipped
+ * (semi-stratified sampling): the first candidate is taken as is.
+ * Output order: the p nonzero samples, then the q zero samples.
+ * Returns ORA_ERR_SAMPLING if some zero sample exhausts max_attempts. */
+int ora_sample_stratified(const ora_tensor* t, int64_t p, int64_t q, uint64_t seed, uint64_t step,
+                          uint64_t client, int64_t max_attempts, int semi,
+                          int64_t* coords_out, double* x_out, double* w_out)
+{
+    const int d = t->d;
+    const int64_t N = t->nnz;
+    const int64_t M = ora_cell_count_i(d, t->dims);
+    if (p < 0 || q < 0 || (p > 0 && N == 0) || (q > 0 && !semi && N >= M)) return ORA_ERR_ARG;
+    const double w_nz = p > 0 ? (double)N / (double)p : 0.0;
+    const double w_z = q > 0 ? (double)(M - N) / (double)q : 0.0;
+    uint64_t key[2] = {seed, client};
+    for (int64_t s = 0; s < p; ++s) {
+        uint64_t ctr[4] = {(uint64_t)s, step, ORA_STREAM_NONZERO, 0};
+        uint64_t out[4];
+        ora_philox4x64_10(ctr, key, out);
+        int64_t j = (int64_t)ora_range(out[0], (uint64_t)N);
+        for (int k = 0; k < d; ++k) coords_out[s * d + k] = t->coords[j * d + k];
+        x_out[s] = t->vals[j];
+        w_out[s] = w_nz;
+    }
+    for (int64_t s = 0; s < q; ++s) {
+        int64_t* idx = coords_out + (p + s) * d;
+        int found_zero = 0;
+        for (int64_t a = 0; a < max_attempts; ++a) {
+            ora_draw_cell(d, t->dims, seed, client, (uint64_t)s, step, ORA_STREAM_ZERO, (uint64_t)a, idx);
+            if (semi || ora_find(t, idx) < 0) { found_zero = 1; break; }
+        }
+        if (!found_zero) return ORA_ERR_SAMPLING;
+        x_out[p + s] = 0.0;
+        w_out[p + s] = w_z;
+    }
+    return ORA_OK;
+}
+
+/* Uniform sampling of a dense tensor (the "several sampling algorithms" of
+ * Sec. 3.1.1; reading: s cells uniform over all M cells with replacement,
+ * weight M/s, x read from the row-major dense array). */
+int ora_sample_uniform(int d, const int64_t* dims, const double* dense, int64_t s_count,
+                       uint64_t seed, uint64_t step, uint64_t client,
+                       int64_t* coords_out, double* x_out, double* w_out)
+{
+    if (d < 1 || d > 8 || s_count < 0) return ORA_ERR_ARG;
+    const double w = s_count > 0 ? ora_cell_count(d, dims) / (double)s_count : 0.0;
+    for (int64_t s = 0; s < s_count; ++s) {
+        int64_t* idx = coords_out + s * d;
+        ora_draw_cell(d, dims, seed, client, (uint64_t)s, step, ORA_STREAM_UNIFORM, 0, idx);
+        int64_t lin = 0;
+        for (int k = 0; k < d; ++k) lin = lin * dims[k] + idx[k];
+        x_out[s] = dense[lin];
+        w_out[s] = w;
+    }
+    return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Losses.  The paper names Poisson (count data) and Gaussian losses and     */
+/* binary data but prints no formula; each loss below is the negative log-  */
+/* likelihood of its distribution with terms depending on x alone dropped.  */
+/*   0 Gaussian:         f = (m - x)^2 / 2,            f' = m - x            */
+/*   1 Poisson (ident.): f = m - x log(m + 1e-10),     f' = 1 - x/(m + 1e-10)*/
+/*   2 Bernoulli-logit:  f = log(1 + e^m) - x m,       f' = 1/(1+e^-m) - x   */
+/* ------------------------------------------------------------------------ */
+
+enum { ORA_LOSS_GAUSSIAN = 0, ORA_LOSS_POISSON = 1, ORA_LOSS_BERNOULLI_LOGIT = 2 };
+#define ORA_POISSON_EPS 1e-10
+
+double ora_f(int loss, double x, double m)
+{
+    switch (loss) {
+    case ORA_LOSS_GAUSSIAN: return 0.5 * (m - x) * (m - x);
+    case ORA_LOSS_POISSON: return m - x * log(m + ORA_POISSON_EPS);
+    case ORA_LOSS_BERNOULLI_LOGIT: {
+        /* log(1 + e^m) written without overflow */
+        double softplus = (m > 0 ? m : 0.0) + log1p(exp(-fabs(m)));
+        return softplus - x * m;
+    }
+    default: return NAN;
+    }
+}
+
+double ora_df(int loss, double x, double m)
+{
+    switch (loss) {
+    case ORA_LOSS_GAUSSIAN: return m - x;
+    case ORA_LOSS_POISSON: return 1.0 - x / (m + ORA_POISSON_EPS);
+    case ORA_LOSS_BERNOULLI_LOGIT: {
+        double sig;
+        if (m >= 0) sig = 1.0 / (1.0 + exp(-m));
+        else { double e = exp(m); sig = e / (1.0 + e); }
+        return sig - x;
+    }
+    default: return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kruskal model entry (eq. cp, elementwise): m = sum_r prod_k A_k[i_k, r]. */
+/* ------------------------------------------------------------------------ */
+
+static void ora_rowoff(int d, const int64_t* dims, int64_t* rowoff)
+{
+    rowoff[0] = 0;
+    for (int k = 1; k <= d; ++k) rowoff[k] = rowoff[k - 1] + dims[k - 1];
+}
+
+double ora_model_value(int d, const int64_t* dims, int R, const double* A, const int64_t* idx)
+{
+    int64_t rowoff[9];
+    ora_rowoff(d, dims, rowoff);
+    double m = 0.0;
+    for (int r = 0; r < R; ++r) {
+        double prod = 1.0;
+        for (int k = 0; k < d; ++k) prod *= A[(rowoff[k] + idx[k]) * R + r];
+        m += prod;
+    }
+    return m;
+}
+
+/* Sampled loss and gradient (eq. gcp-gradient with Y replaced by the sampled
+ * tensor, Sec. 3.1.1-3.1.2), serial MTTKRP over the sample list:
+ *   y_s = w_s f'(x_s, m_s)
+ *   G_k[i_k(s), r] += y_s prod_{n != k} A_n[i_n(s), r]   for every mode k
+ *   F += w_s f(x_s, m_s)
+ * Samples s < n_semi are the nonzero samples of semi-stratified sampling and
+ * use f'(x,m) - f'(0,m) and f(x,m) - f(0,m) instead.  G (sum_k I_k x R) is
+ * overwritten.  Repeated samples are simply summed as separate entries. */
+void ora_loss_grad(int d, const int64_t* dims, int R, const double* A, int64_t n,
+                   const int64_t* coords, const double* x, const double* w, int loss,
+                   int64_t n_semi, double* G, double* F)
+{
+    int64_t rowoff[9];
+    ora_rowoff(d, dims, rowoff);
+    memset(G, 0, sizeof(double) * (size_t)(rowoff[d] * R));
+    double Fsum = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t* idx = coords + s * d;
+        double m = ora_model_value(d, dims, R, A, idx);
+        double y, l;
+        if (s < n_semi) {
+            y = w[s] * (ora_df(loss, x[s], m) - ora_df(loss, 0.0, m));
+            l = w[s] * (ora_f(loss, x[s], m) - ora_f(loss, 0.0, m));
+        } else {
+            y = w[s] * ora_df(loss, x[s], m);
+            l = w[s] * ora_f(loss, x[s], m);
+        }
+        Fsum += l;
+        for (int k = 0; k < d; ++k) {
+            double* g = G + (rowoff[k] + idx[k]) * R;
+            for (int r = 0; r < R; ++r) {
+                double prod = y;
+                for (int nn = 0; nn < d; ++nn)
+                    if (nn != k) prod *= A[(rowoff[nn] + idx[nn]) * R + r];
+                g[r] += prod;
+            }
+        }
+    }
+    if (F) *F = Fsum;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adam update (Alg. adam-update), over the one contiguous parameter vector  */
+/* (Sec. 3.1.3).  t >= 1 counts the updates of this model; epsilon sits      */
+/* inside the square root as the paper writes it; l is the lower bound.     */
+/* ------------------------------------------------------------------------ */
+
+void ora_adam(int64_t n, double* A, const double* G, double* B, double* C, int64_t t,
+              double lr, double beta1, double beta2, double eps, double lower)
+{
+    double c1 = 1.0 - pow(beta1, (double)t);
+    double c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        B[i] = beta1 * B[i] + (1.0 - beta1) * G[i];
+        C[i] = beta2 * C[i] + (1.0 - beta2) * G[i] * G[i];
+        double bhat = B[i] / c1;
+        double chat = C[i] / c2;
+        A[i] = fmax(A[i] - lr * (bhat / sqrt(chat + eps)), lower);
+    }
+}
