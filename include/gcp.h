@@ -1,0 +1,213 @@
+/*
+ * gcp.h -- C ABI of the MI355X (gfx950) library for the sampled stochastic
+ * gradient of GCP tensor decomposition (Myers & Phipps, "Synchronous and
+ * Asynchronous Parallelism Approaches for Generalized Canonical Polyadic
+ * Tensor Decomposition with GenTen", arXiv 2605.20353).
+ *
+ * One step of GCP-SGD/Adam (Alg. gcp-sgd-iter on one device):
+ *   gcp_loss_grad  -- stratified (or uniform / semi-stratified) samples of the
+ *                     tensor, model values m = sum_r prod_k A_k[i_k, r]
+ *                     (eq. cp), y = w f'(x, m), and the sampled MTTKRP
+ *                     G_k[i_k, :] += y prod_{n != k} A_n[i_n, :]
+ *                     (eq. gcp-gradient with the sampled tensor, Sec. 3.1.1-
+ *                     3.1.2), all fused in one kernel;
+ *   gcp_adam_step  -- Alg. adam-update over the one contiguous parameter
+ *                     vector (Sec. 3.1.3).
+ * GCP-FedAdam (Alg. gcp-fed-iter) runs many clients' local steps and the
+ * server step as one batched launch: gcp_fedadam_create / gcp_fedadam_round.
+ *
+ * Conventions for every call:
+ *   - Indices are 0-based.  Coordinates are int64, row-major [n x d].
+ *   - A Kruskal model is ONE contiguous device array of sum_k I_k rows of R
+ *     values, row-major, mode 0's rows first (the paper's single contiguous
+ *     factor array, Sec. 3.1.3).  Gradients and Adam moments use the same
+ *     layout.  No weight vector lambda: m = sum_r prod_k A_k[i_k, r].
+ *   - The tensor's dtype fixes the arithmetic type of every call that uses
+ *     the tensor: values x, weights w, model A, gradient G, device scale.
+ *   - Device pointers are caller-owned (e.g. torch tensors passed as raw
+ *     pointers) unless stated.  The library allocates device memory only in
+ *     the *_create calls, never per step.
+ *   - Every call is asynchronous on the given HIP stream (0 = the null
+ *     stream) and returns a gcp_status.  Argument errors are found on the host
+ *     before anything is launched.  Errors found inside a kernel (a zero
+ *     sample that exhausted its rejection attempts, an out-of-range
+ *     coordinate in a caller-supplied sample list) are recorded in a device
+ *     status word and reported by gcp_device_status.  No C++ exception
+ *     crosses this interface; gcp_last_error gives the calling thread's last
+ *     message.
+ *   - Randomness: Philox4x64-10 (Salmon et al., SC'11), key = (seed, client),
+ *     counter = (s, step, stream | attempt << 8, block), stream 0 = nonzero
+ *     draws, 1 = zero draws, 2 = uniform draws, block = 0 for modes 0-3 and
+ *     1 for modes 4-7.  An index in [0, n) is floor(u n / 2^64) of a 64-bit
+ *     output word u (exact 128-bit product).  Nonzero sample s takes
+ *     j = floor(out0 N / 2^64); zero sample s tries attempts 0, 1, ... with
+ *     i_k = floor(out_k I_k / 2^64) and keeps the first cell that is not a
+ *     stored nonzero.  The same (seed, step, client) always yields the same
+ *     samples, in gcp_sample and inside gcp_loss_grad alike.
+ */
+#ifndef GCP_H
+#define GCP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gcp_status {
+    GCP_OK = 0,
+    GCP_ERR_ARG = -1,          /* invalid argument (found on the host)          */
+    GCP_ERR_HIP = -2,          /* a HIP runtime call failed                     */
+    GCP_ERR_OOM = -3,          /* device allocation failed (create calls only)  */
+    GCP_ERR_SAMPLING = -4,     /* rejection sampling exhausted (device status)  */
+    GCP_ERR_UNSUPPORTED = -5,  /* valid but not supported by this build         */
+    GCP_ERR_DATA = -6          /* bad data found on the device: repeated or
+                                  out-of-range coordinates                      */
+} gcp_status;
+
+typedef enum gcp_dtype { GCP_F32 = 0, GCP_F64 = 1 } gcp_dtype;
+
+/* Losses (negative log-likelihoods, x-only terms dropped):
+ *   GAUSSIAN         f = (m - x)^2 / 2,          f' = m - x
+ *   POISSON          f = m - x log(m + 1e-10),   f' = 1 - x / (m + 1e-10)
+ *                    (identity link; count data, the paper's experiments)
+ *   BERNOULLI_LOGIT  f = log(1 + e^m) - x m,     f' = sigmoid(m) - x          */
+typedef enum gcp_loss {
+    GCP_LOSS_GAUSSIAN = 0,
+    GCP_LOSS_POISSON = 1,
+    GCP_LOSS_BERNOULLI_LOGIT = 2
+} gcp_loss;
+
+/* Sampling schemes (Sec. 3.1.1):
+ *   STRATIFIED       p nonzeros with replacement, weight N/p; q zeros found by
+ *                    rejection against the stored nonzeros, weight (M-N)/q.
+ *   UNIFORM          p cells uniform over all M cells of a DENSE tensor,
+ *                    weight M/p; q must be 0.
+ *   SEMI_STRATIFIED  as STRATIFIED but zero candidates are not searched; the
+ *                    nonzero samples use y = (N/p)(f'(x,m) - f'(0,m)) and the
+ *                    zero samples keep weight (M-N)/q.                       */
+typedef enum gcp_sampling {
+    GCP_SAMPLE_STRATIFIED = 0,
+    GCP_SAMPLE_UNIFORM = 1,
+    GCP_SAMPLE_SEMI_STRATIFIED = 2
+} gcp_sampling;
+
+typedef struct gcp_sample_params {
+    int32_t kind;          /* gcp_sampling                                       */
+    int32_t max_attempts;  /* rejection attempts per zero sample; <= 0 means 64  */
+    int64_t p;             /* nonzero samples (uniform: all samples)             */
+    int64_t q;             /* zero samples (uniform: 0)                          */
+    uint64_t seed;         /* Philox key word 0                                  */
+    uint64_t step;         /* Philox counter word 1 (the iteration number)       */
+    uint64_t client;       /* Philox key word 1 (0 outside GCP-FedAdam)          */
+} gcp_sample_params;
+
+/* A materialised sample list (the sampled tensor of Sec. 3.1.1), caller-owned
+ * device arrays of n = p + q entries in gcp_sample's output order. */
+typedef struct gcp_samples {
+    const int64_t* coords; /* [n x d]                       */
+    const void* x;         /* [n] tensor dtype               */
+    const void* w;         /* [n] tensor dtype               */
+} gcp_samples;
+
+/* Launch shape of the sampled-gradient kernel.  Zero / negative fields take
+ * the library's defaults.  A wavefront takes 64 samples at a time; each
+ * sample's R columns are spread over `lanes` lanes holding `vec` consecutive
+ * columns each (lanes * vec >= R, R % vec == 0). */
+typedef struct gcp_tile {
+    int32_t lanes;      /* 2, 4, 8, 16, 32 or 64                               */
+    int32_t vec;        /* 1, 2 or 4 (f64: 1 or 2)                             */
+    int32_t block;      /* threads per workgroup, multiple of 64, <= 1024      */
+    int32_t grid;       /* workgroups; 0 = sized from occupancy                */
+    int32_t lds_modes;  /* bitmask of modes whose gradient is accumulated in
+                           LDS per workgroup and flushed once; -1 = automatic,
+                           0 = none (global atomics only)                     */
+    int32_t reserved;
+} gcp_tile;
+
+/* gcp_loss_grad flags */
+#define GCP_LOSS_ONLY 1u        /* compute the sampled objective only          */
+#define GCP_ACCUMULATE 2u       /* add into G_out / *loss_out (else overwrite) */
+#define GCP_SCALE_BY_DEV 4u     /* multiply every y by *scale_dev (device
+                                   scalar of the tensor dtype); the objective
+                                   is not scaled                               */
+/* gcp_adam_step flags */
+#define GCP_ADAM_ZERO_GRAD 1u   /* write G = 0 after reading it                */
+
+typedef struct gcp_tensor_s* gcp_tensor;
+typedef struct gcp_fed_s* gcp_fed;
+
+/* Library version string. */
+const char* gcp_version(void);
+
+/* Last error message of the calling thread ("" if none). */
+const char* gcp_last_error(void);
+
+/* Sparse COO tensor (Sec. 3.1.1: N coordinate tuples and N values).
+ * dims_host: d host int64 mode sizes (1 <= d <= 8, I_k >= 1, sum_k
+ * ceil(log2 I_k) <= 63).  coords_dev: device int64 [nnz x d]; vals_dev:
+ * device values of dtype dt.  Copies and packs the nonzeros into 16-byte
+ * device records and builds an open-addressing hash table of the packed
+ * coordinates (the O(1) membership search of Sec. 3.1.1).  The inputs may be
+ * freed after the call returns.  Synchronises the stream: repeated or
+ * out-of-range coordinates return GCP_ERR_DATA.  The handle owns its device
+ * memory until gcp_tensor_destroy. */
+gcp_status gcp_tensor_create(gcp_tensor* out, int d, const int64_t* dims_host, int64_t nnz,
+                             const int64_t* coords_dev, const void* vals_dev, gcp_dtype dt,
+                             hipStream_t stream);
+
+/* Dense tensor of prod_k I_k values, row-major (last mode fastest), for
+ * UNIFORM sampling.  BORROWS vals_dev: the caller keeps it alive and
+ * unchanged while the handle is used. */
+gcp_status gcp_tensor_create_dense(gcp_tensor* out, int d, const int64_t* dims_host,
+                                   const void* vals_dev, gcp_dtype dt, hipStream_t stream);
+
+/* Frees the handle's device memory (synchronises its device first). */
+gcp_status gcp_tensor_destroy(gcp_tensor t);
+
+/* Bytes of device memory the handle owns. */
+int64_t gcp_tensor_device_bytes(gcp_tensor t);
+
+/* Synchronises the stream, then reports and clears the handle's device
+ * status word: GCP_OK, GCP_ERR_SAMPLING or GCP_ERR_DATA. */
+gcp_status gcp_device_status(gcp_tensor t, hipStream_t stream);
+
+/* Materialises the sample list (Sec. 3.1.1): n = p + q samples, the p
+ * nonzero samples first.  coords_out [n x d] int64, x_out [n] and w_out [n]
+ * of the tensor dtype, all device, caller-owned.  Bit-exact reproducible. */
+gcp_status gcp_sample(gcp_tensor t, const gcp_sample_params* sp, int64_t* coords_out,
+                      void* x_out, void* w_out, hipStream_t stream);
+
+/* Sampled objective and gradient, fused (Sec. 3.1.2 "Fused Sampling-MTTKRP",
+ * here with stratified, uniform or semi-stratified sampling).
+ *   smp == NULL: the samples of `sp` are drawn inside the kernel and never
+ *                stored (identical to what gcp_sample returns for `sp`);
+ *   smp != NULL: the materialised list is read instead (sp->kind and sp->p
+ *                still say which entries are semi-stratified nonzeros).
+ * A: device model [sum_k I_k x R], 1 <= R <= 256.  G_out: device gradient of
+ * the same shape (may be NULL with GCP_LOSS_ONLY).  loss_out: device double
+ * receiving F~ = sum_s w_s f(x_s, m_s) (NULL = not computed).  Unless
+ * GCP_ACCUMULATE is set, G_out and *loss_out are overwritten.  tile: launch
+ * shape (NULL = defaults).  Duplicate samples are summed as separate entries;
+ * atomics make the summation order unspecified. */
+gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, const gcp_samples* smp,
+                         const void* A, int R, gcp_loss loss, unsigned flags,
+                         const void* scale_dev, void* G_out, double* loss_out,
+                         const gcp_tile* tile, hipStream_t stream);
+
+/* Alg. adam-update on n contiguous parameters of dtype dt, one launch:
+ *   B = b1 B + (1-b1) G;  C = b2 C + (1-b2) G*G;
+ *   A = max(A - lr (B/(1-b1^t)) / sqrt(C/(1-b2^t) + eps), lower)
+ * (epsilon inside the square root, as the paper writes it; lower = -INFINITY
+ * disables the bound).  t >= 1 is this model's update count.  A, B, C are
+ * updated in place; G is read (and zeroed with GCP_ADAM_ZERO_GRAD). */
+gcp_status gcp_adam_step(void* A, void* G, void* B, void* C, int64_t n, gcp_dtype dt, int64_t t,
+                         double lr, double beta1, double beta2, double eps, double lower,
+                         unsigned flags, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCP_H */

@@ -1,0 +1,339 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Samples must match bit for bit.  Gradients are compared per mode as
+||G_gpu - G_oracle||_F / ||G_oracle||_F with the oracle fed the same factors
+(float32 factors upcast to float64): <= 1e-12 for the float64 build and
+<= 1e-5 for float32.  Sampled objectives: same relative bounds.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_20353_amd import _lib as G
+from paper_2605_20353_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+LOSSES = ["poisson", "gaussian", "bernoulli_logit"]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------ cases --
+
+CASES = {
+    # name: dims, nnz, R
+    "cfg1_50x40x30": ([50, 40, 30], 3000, 5),
+    "4way": ([12, 10, 8, 6], 400, 8),
+    "5way": ([6, 5, 4, 3, 7], 150, 3),
+    "1way": ([300], 40, 4),
+    "r32": ([64, 48, 40], 2000, 32),
+    "r64_4way": ([30, 20, 16, 8], 900, 64),
+}
+
+
+def make_case(name, dtype, gpu, binary=False, seed=2606):
+    dims, nnz, R = CASES[name]
+    data = synth.count_tensor(dims, 3, nnz, seed=seed, binary=binary)
+    coords = data.coords
+    vals = data.vals
+    t_gpu = G.SparseTensor(dims, coords.to(gpu), vals.to(dtype).to(gpu))
+    # the oracle sees exactly the values the GPU holds
+    t_ora = oracle.SparseTensor(dims, coords.numpy(), vals.to(dtype).double().numpy())
+    return t_gpu, t_ora, dims, R
+
+
+def model(dims, R, dtype, gpu, seed=7, dist="uniform", lo=0.2):
+    A = synth.init_model(dims, R, seed, dist=dist, dtype=torch.float64)
+    if dist == "uniform":
+        A = lo + (1 - lo) * A
+    return A.to(dtype).to(gpu).contiguous()
+
+
+def split_rel_err(g_gpu, g_ora, dims, R):
+    g_gpu = g_gpu.reshape(-1, R)
+    g_ora = g_ora.reshape(-1, R)
+    errs, off = [], 0
+    for n in dims:
+        a, b = g_gpu[off:off + n], g_ora[off:off + n]
+        nb = np.linalg.norm(b)
+        errs.append(np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a))
+        off += n
+    return max(errs)
+
+
+def oracle_grad(t_ora, dims, R, A, loss, sp: G.SampleParams):
+    semi = sp.kind == "semi_stratified"
+    sc, sx, sw = oracle.sample_stratified(t_ora, sp.p, sp.q, sp.seed, sp.step, sp.client,
+                                          sp.max_attempts, semi=semi)
+    A64 = A.double().cpu().numpy().reshape(-1)
+    return oracle.loss_grad(dims, R, A64, sc, sx, sw, loss, n_semi=sp.p if semi else 0)
+
+
+# --------------------------------------------------------------- sampling --
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("pq", [(1000, 1000), (37, 91), (0, 64), (65, 0)])
+def test_samples_bit_exact(gpu, dtype, name, pq):
+    t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
+    p, q = pq
+    sp = G.SampleParams("stratified", p, q, seed=20353, step=11, client=3)
+    say(f"sample {name} {dtype} p={p} q={q}")
+    c, x, w = G.gcp_sample(t_gpu, sp)
+    t_gpu.status()
+    oc, ox, ow = oracle.sample_stratified(t_ora, p, q, 20353, 11, 3)
+    np.testing.assert_array_equal(c.cpu().numpy(), oc)
+    np.testing.assert_array_equal(x.cpu().numpy(), ox.astype(x.cpu().numpy().dtype))
+    np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
+
+
+def test_samples_depend_on_step_seed_client(gpu):
+    t_gpu, _, _, _ = make_case("cfg1_50x40x30", torch.float64, gpu)
+    base = G.gcp_sample(t_gpu, G.SampleParams("stratified", 100, 100, seed=1, step=0, client=0))[0]
+    for kw in (dict(seed=2), dict(step=1), dict(client=1)):
+        args = dict(seed=1, step=0, client=0)
+        args.update(kw)
+        other = G.gcp_sample(t_gpu, G.SampleParams("stratified", 100, 100, **args))[0]
+        assert not torch.equal(base, other)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_uniform_samples_bit_exact(gpu, dtype):
+    dims = [6, 5, 4, 3]
+    X, _ = synth.dense_gaussian(dims, 2, seed=3, dtype=torch.float64)
+    Xg = X.to(dtype).to(gpu)
+    t = G.DenseTensor(dims, Xg)
+    sp = G.SampleParams("uniform", 333, 0, seed=5, step=2)
+    c, x, w = G.gcp_sample(t, sp)
+    oc, ox, ow = oracle.sample_uniform(dims, X.to(dtype).double().numpy(), 333, 5, 2)
+    np.testing.assert_array_equal(c.cpu().numpy(), oc)
+    np.testing.assert_array_equal(x.double().cpu().numpy(), ox)
+    np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_semi_stratified_samples_bit_exact(gpu, dtype):
+    t_gpu, t_ora, dims, R = make_case("4way", dtype, gpu)
+    sp = G.SampleParams("semi_stratified", 200, 300, seed=9, step=4)
+    c, x, w = G.gcp_sample(t_gpu, sp)
+    oc, ox, ow = oracle.sample_stratified(t_ora, 200, 300, 9, 4, semi=True)
+    np.testing.assert_array_equal(c.cpu().numpy(), oc)
+    np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
+
+
+# --------------------------------------------------------------- gradient --
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("loss", LOSSES)
+@pytest.mark.parametrize("name", list(CASES))
+def test_fused_loss_grad_matches_oracle(gpu, dtype, loss, name):
+    t_gpu, t_ora, dims, R = make_case(name, dtype, gpu, binary=(loss == "bernoulli_logit"))
+    dist = "normal" if loss != "poisson" else "uniform"
+    A = model(dims, R, dtype, gpu, dist=dist)
+    sp = G.SampleParams("stratified", 1500, 1300, seed=77, step=5)
+    say(f"loss_grad {name} {loss} {dtype}")
+    Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, loss)
+    t_gpu.status()
+    Go, Fo = oracle_grad(t_ora, dims, R, A, loss, sp)
+    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+    assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+def _shapes(R, dtype):
+    f32 = [(8, 1), (16, 1), (32, 1), (64, 1), (2, 4), (4, 4), (8, 4), (16, 4), (32, 4), (64, 4), (4, 2), (8, 2), (16, 2)]
+    f64 = [(8, 1), (16, 1), (32, 1), (64, 1), (4, 2), (8, 2), (16, 2), (32, 2)]
+    out = []
+    for lanes, vec in (f32 if dtype == torch.float32 else f64):
+        if R % vec == 0 and lanes * vec >= R:
+            out.append((lanes, vec))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", ["r32", "r64_4way", "cfg1_50x40x30"])
+def test_every_tile_matches_oracle(gpu, dtype, name):
+    t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
+    A = model(dims, R, dtype, gpu)
+    sp = G.SampleParams("stratified", 777, 555, seed=3, step=1)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    for lanes, vec in _shapes(R, dtype):
+        for block in (64, 256, 1024):
+            for lds in (0, (1 << len(dims)) - 1):
+                tile = G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=lds)
+                Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=tile)
+                err = split_rel_err(Gg.double().cpu().numpy(), Go, dims, R)
+                assert err <= TOL[dtype], (lanes, vec, block, lds, err)
+                assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+    # a small grid forces many chunks per wave (grid-stride path)
+    Gg, _ = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(grid=1, block=64))
+    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_materialised_equals_fused(gpu, dtype):
+    t_gpu, t_ora, dims, R = make_case("4way", dtype, gpu)
+    A = model(dims, R, dtype, gpu)
+    sp = G.SampleParams("stratified", 900, 700, seed=12, step=2)
+    smp = G.gcp_sample(t_gpu, sp)
+    Gm, Lm = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", samples=smp)
+    Gf, Lf = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson")
+    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    for Gx, Lx in ((Gm, Lm), (Gf, Lf)):
+        assert split_rel_err(Gx.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+        assert abs(Lx.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("loss", LOSSES)
+def test_semi_stratified_grad_matches_oracle(gpu, dtype, loss):
+    t_gpu, t_ora, dims, R = make_case("r32", dtype, gpu, binary=(loss == "bernoulli_logit"))
+    A = model(dims, R, dtype, gpu, dist="normal" if loss != "poisson" else "uniform")
+    sp = G.SampleParams("semi_stratified", 1000, 1200, seed=8, step=3)
+    Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, loss)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, loss, sp)
+    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+    assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_uniform_dense_grad_matches_oracle(gpu, dtype):
+    dims, R = [20, 16, 12, 6], 16
+    X, _ = synth.dense_gaussian(dims, 4, seed=3, dtype=torch.float64)
+    t = G.DenseTensor(dims, X.to(dtype).to(gpu))
+    A = model(dims, R, dtype, gpu, dist="normal")
+    sp = G.SampleParams("uniform", 5000, 0, seed=4, step=0)
+    for lds in (-1, 0, 15):
+        Gg, Lg = G.gcp_loss_grad(t, sp, A, R, "gaussian", tile=G.Tile(lds_modes=lds))
+        oc, ox, ow = oracle.sample_uniform(dims, X.to(dtype).double().numpy(), 5000, 4, 0)
+        Go, Fo = oracle.loss_grad(dims, R, A.double().cpu().numpy(), oc, ox, ow, "gaussian")
+        assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+        assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_flags_scale_accumulate_loss_only(gpu, dtype):
+    t_gpu, t_ora, dims, R = make_case("cfg1_50x40x30", dtype, gpu)
+    A = model(dims, R, dtype, gpu)
+    sp = G.SampleParams("stratified", 500, 500, seed=1, step=0)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    scale = torch.tensor([-2.5], dtype=dtype, device=gpu)
+    Gs, Ls = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", scale=scale)
+    assert split_rel_err(Gs.double().cpu().numpy(), -2.5 * Go, dims, R) <= TOL[dtype]
+    assert abs(Ls.item() - Fo) <= TOL[dtype] * abs(Fo)            # objective not scaled
+    Ga, La = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", G=Gs.clone(), loss_out=Ls.clone(), accumulate=True)
+    assert split_rel_err(Ga.double().cpu().numpy(), -1.5 * Go, dims, R) <= 10 * TOL[dtype]
+    assert abs(La.item() - 2 * Fo) <= TOL[dtype] * abs(2 * Fo)
+    _, Lo = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", loss_only=True)
+    assert abs(Lo.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+# ------------------------------------------------------------------- Adam --
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [1, 7, 1000, 4099])
+def test_adam_matches_oracle(gpu, dtype, n):
+    rng = np.random.default_rng(n)
+    A0 = rng.normal(size=n)
+    Gr = rng.normal(size=n)
+    B0 = rng.normal(size=n) * 0.1
+    C0 = rng.uniform(0, 1, n)
+    dev = lambda a: torch.tensor(a, dtype=dtype, device=gpu)
+    A, Gt, B, Cm = dev(A0), dev(Gr), dev(B0), dev(C0)
+    G.gcp_adam_step(A, Gt, B, Cm, 3, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-8, lower=-0.5, zero_grad=True)
+    Ao, Bo, Co = (v.to(dtype).double().cpu().numpy() for v in (dev(A0), dev(B0), dev(C0)))
+    oracle.adam(Ao, dev(Gr).double().cpu().numpy(), Bo, Co, 3, 1e-2, 0.9, 0.99, 1e-8, -0.5)
+    tol = 1e-14 if dtype == torch.float64 else 1e-6
+    np.testing.assert_allclose(A.double().cpu().numpy(), Ao, rtol=tol, atol=tol)
+    np.testing.assert_allclose(B.double().cpu().numpy(), Bo, rtol=tol, atol=tol)
+    np.testing.assert_allclose(Cm.double().cpu().numpy(), Co, rtol=tol, atol=tol)
+    assert torch.count_nonzero(Gt).item() == 0
+
+
+def test_config1_fp64_trajectory_20_steps(gpu):
+    """50x40x30 Poisson, rank 5, 1000 + 1000 samples, 20 Adam steps, lr 1e-3:
+    the FP64 GPU trajectory equals the oracle's within 1e-10 relative."""
+    t_gpu, t_ora, dims, R = make_case("cfg1_50x40x30", torch.float64, gpu)
+    A = model(dims, R, torch.float64, gpu, seed=2605, lo=0.0)
+    Bg, Cg, Gg = torch.zeros_like(A), torch.zeros_like(A), torch.zeros_like(A)
+    Ao = A.cpu().numpy().copy()
+    Bo, Co = np.zeros_like(Ao), np.zeros_like(Ao)
+    ap = oracle.AdamParams(lr=1e-3, lower=0.0)
+    for step in range(20):
+        sp = G.SampleParams("stratified", 1000, 1000, seed=20353, step=step)
+        G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", G=Gg, want_loss=False)
+        G.gcp_adam_step(A, Gg, Bg, Cg, step + 1, lr=1e-3, lower=0.0)
+        oracle.sgd_step(t_ora, R, Ao, Bo, Co, step + 1, "poisson", 1000, 1000, 20353, step, ap)
+    t_gpu.status()
+    err = np.linalg.norm(A.cpu().numpy() - Ao) / np.linalg.norm(Ao)
+    assert err <= 1e-10, err
+
+
+# ----------------------------------------------------------------- errors --
+
+def test_rejection_exhaustion_is_reported(gpu):
+    dims = [4, 3, 2]
+    allc = torch.tensor(list(np.ndindex(*dims)), dtype=torch.int64)
+    t = G.SparseTensor(dims, allc[1:].to(gpu), torch.ones(23, dtype=torch.float64, device=gpu))
+    G.gcp_sample(t, G.SampleParams("stratified", 0, 64, seed=1, max_attempts=1))
+    with pytest.raises(G.GCPError) as e:
+        t.status()
+    assert e.value.code == G.GCP_ERR_SAMPLING
+    t.status()                                   # the word was cleared
+    c, _, _ = G.gcp_sample(t, G.SampleParams("stratified", 0, 16, seed=1, max_attempts=2000))
+    t.status()
+    assert (c.cpu() == allc[0]).all()
+
+
+def test_bad_data_is_rejected(gpu):
+    dims = [4, 4]
+    with pytest.raises(G.GCPError) as e:
+        G.SparseTensor(dims, torch.tensor([[0, 1], [2, 3], [0, 1]], device=gpu),
+                       torch.ones(3, dtype=torch.float64, device=gpu))
+    assert e.value.code == G.GCP_ERR_DATA
+    with pytest.raises(G.GCPError) as e:
+        G.SparseTensor(dims, torch.tensor([[0, 4]], device=gpu), torch.ones(1, dtype=torch.float64, device=gpu))
+    assert e.value.code == G.GCP_ERR_DATA
+    t = G.SparseTensor(dims, torch.tensor([[0, 1]], device=gpu), torch.ones(1, dtype=torch.float64, device=gpu))
+    A = torch.ones(8 * 2, dtype=torch.float64, device=gpu)
+    bad = (torch.tensor([[0, 9]], device=gpu), torch.ones(1, dtype=torch.float64, device=gpu),
+           torch.ones(1, dtype=torch.float64, device=gpu))
+    G.gcp_loss_grad(t, G.SampleParams("stratified", 1, 0), A, 2, "poisson", samples=bad)
+    with pytest.raises(G.GCPError) as e:
+        t.status()
+    assert e.value.code == G.GCP_ERR_DATA
+
+
+def test_argument_errors(gpu):
+    t_gpu, _, dims, R = make_case("cfg1_50x40x30", torch.float32, gpu)
+    A = model(dims, R, torch.float32, gpu)
+    with pytest.raises(G.GCPError):      # no zeros to sample in a full tensor
+        full = torch.tensor(list(np.ndindex(2, 2)), device=gpu)
+        tf = G.SparseTensor([2, 2], full, torch.ones(4, device=gpu))
+        G.gcp_sample(tf, G.SampleParams("stratified", 1, 1))
+    with pytest.raises(G.GCPError):      # uniform sampling needs a dense tensor
+        G.gcp_sample(t_gpu, G.SampleParams("uniform", 10, 0))
+    with pytest.raises(G.GCPError):      # vec does not divide R = 5
+        G.gcp_loss_grad(t_gpu, G.SampleParams("stratified", 10, 10), A, R, "poisson", tile=G.Tile(vec=4))
+    with pytest.raises(G.GCPError):      # too few lanes
+        G.gcp_loss_grad(t_gpu, G.SampleParams("stratified", 10, 10), A, R, "poisson", tile=G.Tile(lanes=2, vec=1))
+    with pytest.raises(G.GCPError):      # R outside [1, 256]
+        G.gcp_loss_grad(t_gpu, G.SampleParams("stratified", 10, 10), torch.zeros(0, device=gpu), 0, "poisson")
+    assert G.lib().gcp_loss_grad(t_gpu.handle, None, None, None, 0, 1, 0, None, None, None, None,
+                                 None) == G.GCP_ERR_ARG
+
+
+def test_empty_sample_set(gpu):
+    t_gpu, _, dims, R = make_case("cfg1_50x40x30", torch.float32, gpu)
+    A = model(dims, R, torch.float32, gpu)
+    Gg, Lg = G.gcp_loss_grad(t_gpu, G.SampleParams("stratified", 0, 0), A, R, "poisson",
+                             G=torch.full_like(A, 3.0))
+    assert torch.count_nonzero(Gg).item() == 0 and Lg.item() == 0.0
