@@ -117,13 +117,24 @@ typedef struct gcp_samples {
  * columns each (lanes * vec >= R, R % vec == 0). */
 typedef struct gcp_tile {
     int32_t lanes;      /* 2, 4, 8, 16, 32 or 64                               */
-    int32_t vec;        /* 1, 2 or 4 (f64: 1 or 2)                             */
+    int32_t vec;        /* 1, 2 or 4                                           */
     int32_t block;      /* threads per workgroup, multiple of 64, <= 1024      */
-    int32_t grid;       /* workgroups; 0 = sized from occupancy                */
-    int32_t lds_modes;  /* bitmask of modes whose gradient is accumulated in
-                           LDS per workgroup and flushed once; -1 = automatic,
-                           0 = none (global atomics only)                     */
-    int32_t reserved;
+    int32_t grid;       /* workgroups; 0 = sized from occupancy (ignored when
+                           any mode is bucketed)                              */
+    int32_t lds_modes;  /* bitmask of modes whose whole gradient is
+                           accumulated in LDS per workgroup and flushed once;
+                           -1 = automatic, 0 = none                           */
+    int32_t bucket_modes; /* bitmask of modes scattered by row blocks (sort
+                           by row, LDS accumulation per block, one flush);
+                           needs gcp_tensor_reserve; -1 = automatic (every
+                           mode not in LDS when a workspace is reserved and
+                           p + q >= 65536), 0 = none                          */
+    int32_t bucket_lds_bytes;     /* LDS bytes of one row block (rows are a
+                                     power of two); 0 = 32768, min 8192     */
+    int32_t bucket_block_samples; /* samples sorted per workgroup, multiple
+                                     of 64 in [512, 8192]; 0 = 2048          */
+    int32_t bucket_splits;        /* workgroups per row block; 0 = auto     */
+    int32_t bucket_block;         /* threads per row-block workgroup; 0 = 512 */
 } gcp_tile;
 
 /* gcp_loss_grad flags */
@@ -143,6 +154,11 @@ const char* gcp_version(void);
 
 /* Last error message of the calling thread ("" if none). */
 const char* gcp_last_error(void);
+
+/* sizeof of an ABI struct by name ("gcp_sample_params", "gcp_samples",
+ * "gcp_tile", "gcp_fed_client", "gcp_fed_desc"), -1 if unknown: lets a
+ * binding check its mirror of the layouts. */
+int64_t gcp_struct_size(const char* name);
 
 /* Sparse COO tensor (Sec. 3.1.1: N coordinate tuples and N values).
  * dims_host: d host int64 mode sizes (1 <= d <= 8, I_k >= 1, sum_k
@@ -168,6 +184,15 @@ gcp_status gcp_tensor_destroy(gcp_tensor t);
 
 /* Bytes of device memory the handle owns. */
 int64_t gcp_tensor_device_bytes(gcp_tensor t);
+
+/* Reserves the handle's workspace for the row-bucketed gradient scatter
+ * (sort-by-row MTTKRP, Sec. 3.1.2) for calls with up to max_samples = p + q
+ * samples at rank R: about 16 (max_samples + 8192) d bytes of sample entries
+ * plus per-(row block, workgroup) counts.  Without a reservation every large
+ * mode uses hardware atomics.  Calls that use the workspace of one handle
+ * must be ordered (one stream, or synchronised); concurrent calls race.
+ * Replaces any earlier reservation (synchronises the device first). */
+gcp_status gcp_tensor_reserve(gcp_tensor t, int64_t max_samples, int R, hipStream_t stream);
 
 /* Synchronises the stream, then reports and clears the handle's device
  * status word: GCP_OK, GCP_ERR_SAMPLING or GCP_ERR_DATA. */
@@ -205,6 +230,86 @@ gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, const gcp_sa
 gcp_status gcp_adam_step(void* A, void* G, void* B, void* C, int64_t n, gcp_dtype dt, int64_t t,
                          double lr, double beta1, double beta2, double eps, double lower,
                          unsigned flags, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* GCP-FedAdam (Alg. gcp-fed-iter): K clients, each holding one block of a   */
+/* d-way block grid over the tensor, run tau local GCP-Adam steps on their   */
+/* own model; then the server model takes one Adam step whose gradient is    */
+/* the per-row mean of the deltas D = U - M_c over the clients whose block   */
+/* covers the row (the all-reduce over slice groups, here within one GPU).   */
+/* One round (gcp_fedadam_round with round r) is:                            */
+/*   1. M_c <- rows of U covered by client c, for every c;                    */
+/*   2. tau local steps j = 0..tau-1 per client: stratified samples of the    */
+/*      client's block with Philox key (seed, c) and step r*tau + j, sampled  */
+/*      gradient into G_c, Adam on (M_c, B_c, C_c) with t = r*tau + j + 1;     */
+/*   3. D = per-row mean over covering clients of U - M_c;                    */
+/*   4. Adam on (U, B_s, C_s) with gradient D, lr = meta_lr, t = r + 1.       */
+/* Client moments persist across rounds; only M_c is reset to U.            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct gcp_fed_client {
+    gcp_tensor tensor;        /* the client's block, block-local coordinates       */
+    int64_t row_base[8];      /* global index of the block's first row, per mode   */
+    void* M;                  /* client model [sum_k I_k^c x R], device            */
+    void* B;                  /* client Adam moments, same shape                   */
+    void* C;
+    void* G;                  /* client gradient buffer, same shape; must hold
+                                 zeros before the first round (it is left zeroed
+                                 after every round)                               */
+} gcp_fed_client;
+
+typedef struct gcp_fed_desc {
+    int32_t nclients;         /* K >= 1                                           */
+    int32_t R;                /* rank                                             */
+    int32_t tau;              /* local steps per round >= 1                       */
+    int32_t loss;             /* gcp_loss                                         */
+    int32_t batched;          /* 1: the clients' local steps run as ONE persistent
+                                 launch per round; 0: one sampled-gradient launch
+                                 and one Adam launch per client and local step    */
+    int32_t use_graph;        /* batched only: capture the round's launches into
+                                 a HIP graph on the first round, replay after     */
+    int32_t workgroups_per_client; /* batched launch shape, 0 = automatic        */
+    int32_t block;            /* threads per workgroup (batched), 0 = 256         */
+    int32_t lanes;            /* lane shape of the gradient part, 0 = default    */
+    int32_t vec;
+    int32_t max_attempts;     /* rejection attempts per zero sample, <= 0 = 64   */
+    int32_t reserved;
+    int64_t p;                /* nonzero samples per client and local step       */
+    int64_t q;                /* zero samples per client and local step          */
+    uint64_t seed;
+    int64_t global_dims[8];   /* d = the clients' tensor order                   */
+    void* U;                  /* server model [sum_k I_k x R], device            */
+    void* Bs;                 /* server Adam moments, same shape                 */
+    void* Cs;
+    double lr;                /* client Adam rate                                 */
+    double meta_lr;           /* server Adam rate (meta-rate)                     */
+    double beta1, beta2, eps, lower;   /* shared by client and server Adam       */
+    const gcp_fed_client* clients;     /* host array of nclients entries         */
+} gcp_fed_desc;
+
+/* Validates the description, copies it, and builds the device-side client
+ * table and the row-coverage table of the server step.  Every buffer stays
+ * caller-owned; the tensors must outlive the handle.  The clients' blocks
+ * must lie inside global_dims.  A batched handle needs all its workgroups
+ * resident at once (K * workgroups_per_client <= what the GPU holds):
+ * GCP_ERR_UNSUPPORTED otherwise. */
+gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_t stream);
+
+/* Runs round `round` (see above) asynchronously on the stream.  Batched
+ * rounds are one persistent kernel for all clients and tau steps plus one
+ * server kernel (a HIP graph replay when use_graph is set; the graph is
+ * bound to the stream of its first capture).  The persistent kernel's
+ * barriers give up after a bounded wait and record GCP_ERR_HIP in the
+ * handle's status rather than hang. */
+gcp_status gcp_fedadam_round(gcp_fed f, int64_t round, hipStream_t stream);
+
+/* Synchronises the stream; reports a barrier timeout of a batched round
+ * (GCP_ERR_HIP) or a sampling error of any client tensor (GCP_ERR_SAMPLING),
+ * and clears them. */
+gcp_status gcp_fedadam_status(gcp_fed f, hipStream_t stream);
+
+/* Frees the handle (its graph and device tables; not the caller's buffers). */
+gcp_status gcp_fedadam_destroy(gcp_fed f);
 
 #ifdef __cplusplus
 }

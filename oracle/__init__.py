@@ -157,8 +157,11 @@ class SparseTensor:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().ora_tensor_free(h)
+        if h and _lib is not None:
+            try:
+                _lib.ora_tensor_free(h)
+            except Exception:
+                pass
             self._h = None
 
     @property

@@ -5,6 +5,8 @@ as hand-written HIP kernels behind the C ABI in include/gcp.h.
 """
 from ._lib import (  # noqa: F401
     GCPError, SampleParams, Tile, SparseTensor, DenseTensor,
-    gcp_tensor_create, gcp_tensor_create_dense, gcp_tensor_destroy, gcp_device_status,
+    gcp_tensor_create, gcp_tensor_create_dense, gcp_tensor_destroy, gcp_tensor_reserve, gcp_device_status,
     gcp_sample, gcp_loss_grad, gcp_adam_step, lib,
 )
+from .autograd import GCPLoss, KruskalModel, gcp_loss  # noqa: F401,E402
+from .fedadam import FedAdam, FedConfig, FedTile  # noqa: F401,E402

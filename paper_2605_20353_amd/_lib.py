@@ -59,7 +59,8 @@ class gcp_samples(C.Structure):
 
 class gcp_tile(C.Structure):
     _fields_ = [("lanes", C.c_int32), ("vec", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
-                ("lds_modes", C.c_int32), ("reserved", C.c_int32)]
+                ("lds_modes", C.c_int32), ("bucket_modes", C.c_int32), ("bucket_lds_bytes", C.c_int32),
+                ("bucket_block_samples", C.c_int32), ("bucket_splits", C.c_int32), ("bucket_block", C.c_int32)]
 
 
 _lock = threading.Lock()
@@ -75,6 +76,7 @@ def _declare(L):
         "gcp_tensor_create_dense": ([C.POINTER(vp), C.c_int, C.POINTER(i64), vp, C.c_int, vp], C.c_int),
         "gcp_tensor_destroy": ([vp], C.c_int),
         "gcp_tensor_device_bytes": ([vp], i64),
+        "gcp_tensor_reserve": ([vp, i64, C.c_int, vp], C.c_int),
         "gcp_device_status": ([vp, vp], C.c_int),
         "gcp_sample": ([vp, C.POINTER(gcp_sample_params), vp, vp, vp, vp], C.c_int),
         "gcp_loss_grad": ([vp, C.POINTER(gcp_sample_params), C.POINTER(gcp_samples), vp, C.c_int, C.c_int,
@@ -164,6 +166,7 @@ class SparseTensor:
                                        _dt(self.dtype), _stream(stream)), "gcp_tensor_create")
         self._h = h
         self.dense = False
+        self.reserved_samples = 0
 
     @property
     def handle(self):
@@ -182,6 +185,11 @@ class SparseTensor:
 
     def device_bytes(self) -> int:
         return int(lib().gcp_tensor_device_bytes(self._h))
+
+    def reserve(self, max_samples: int, R: int, stream=None) -> None:
+        """Workspace for the row-bucketed scatter (gcp_tensor_reserve)."""
+        _check(lib().gcp_tensor_reserve(self._h, int(max_samples), int(R), _stream(stream)), "gcp_tensor_reserve")
+        self.reserved_samples = int(max_samples)
 
     def status(self, stream=None) -> None:
         _check(lib().gcp_device_status(self._h, _stream(stream)), "gcp_device_status")
@@ -228,6 +236,10 @@ def gcp_tensor_create_dense(dims, vals, stream=None) -> DenseTensor:
     return DenseTensor(dims, vals, stream)
 
 
+def gcp_tensor_reserve(t: SparseTensor, max_samples: int, R: int, stream=None) -> None:
+    t.reserve(max_samples, R, stream)
+
+
 def gcp_tensor_destroy(t: SparseTensor) -> None:
     t.close()
 
@@ -265,9 +277,15 @@ class Tile:
     block: int = 0
     grid: int = 0
     lds_modes: int = -1
+    bucket_modes: int = -1
+    bucket_lds_bytes: int = 0
+    bucket_block_samples: int = 0
+    bucket_splits: int = 0
+    bucket_block: int = 0
 
     def c(self) -> gcp_tile:
-        return gcp_tile(self.lanes, self.vec, self.block, self.grid, self.lds_modes, 0)
+        return gcp_tile(self.lanes, self.vec, self.block, self.grid, self.lds_modes, self.bucket_modes,
+                        self.bucket_lds_bytes, self.bucket_block_samples, self.bucket_splits, self.bucket_block)
 
 
 def gcp_sample(t: SparseTensor, sp: SampleParams, stream=None):

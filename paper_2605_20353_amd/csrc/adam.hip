@@ -24,11 +24,7 @@ struct AdamArgs {
 template <typename T>
 __device__ __forceinline__ void adam_elem(const AdamArgs<T>& a, T& p, T g, T& b, T& c)
 {
-    b = a.b1 * b + a.one_m_b1 * g;
-    c = a.b2 * c + a.one_m_b2 * g * g;
-    const T bhat = b / a.c1;
-    const T chat = c / a.c2;
-    p = fmax(p - a.lr * (bhat / sqrt(chat + a.eps)), a.lower);
+    adam_update<T>(p, g, b, c, a.lr, a.b1, a.b2, a.one_m_b1, a.one_m_b2, a.c1, a.c2, a.eps, a.lower);
 }
 
 template <typename T>

@@ -1,0 +1,583 @@
+// GCP-FedAdam (Alg. gcp-fed-iter) on one GPU: every client's local GCP-Adam
+// steps in one persistent launch, then one server kernel that averages the
+// deltas per row and takes the server Adam step.
+//
+// Persistent launch: client c owns W consecutive workgroups.  Per round they
+// copy the client's rows of the server model into M_c, then for each of the
+// tau local steps: the sampled gradient of the client's block (the same
+// per-chunk body as gcp_loss_grad, hardware atomics into G_c), a group
+// barrier, Adam on M_c (which also re-zeroes G_c), a group barrier.  The
+// barrier is a per-client arrival counter in global memory with bounded
+// spinning: all K*W workgroups must be resident (checked at create), and a
+// barrier that waits too long records an error instead of hanging.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "lg_core.hpp"
+
+namespace gcp {
+
+constexpr uint32_t kStatusBarrier = 4u;
+constexpr long kSpinLimit = 1L << 22;
+
+template <typename T>
+struct FedClientDev {
+    LGParams<T> P;                 // P.A = M_c, P.G = G_c, P.sc = the block's sampler
+    T* B;
+    T* C;
+    int64_t nparams;               // sum_k I_k^c * R
+    int64_t seg_src[kMaxModes];    // first server element of the block's rows in mode k
+    int64_t seg_dst[kMaxModes];    // first client element of mode k
+    int64_t seg_len[kMaxModes];    // elements of mode k (I_k^c * R)
+};
+
+template <typename T>
+struct FedArgs {
+    const FedClientDev<T>* clients;
+    int K, W, tau, d, R;
+    T* U;
+    T* Bs;
+    T* Cs;
+    int64_t nserver;               // server elements
+    T lr, meta, b1, b2, one_m_b1, one_m_b2, eps, lower;
+    double b1d, b2d;
+    int* barrier;                  // [K] arrival counters, zero between rounds
+    const int64_t* round;          // device round number
+    uint32_t* status;
+    const int64_t* cov_ptr;        // per server row: clients covering it (CSR)
+    const int* cov_client;
+    const int* cov_lrow;           // the row's index in the client's model
+    T* const* Mptrs;               // per client model
+};
+
+__device__ __forceinline__ void fed_barrier(int* ctr, int target, uint32_t* status)
+{
+    __threadfence();               // this thread's atomics and stores are performed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(ctr, 1);
+        if (!(__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusBarrier)) {
+            for (long spin = 0; __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target; ++spin) {
+                if (spin > kSpinLimit) {
+                    atomicOr(status, kStatusBarrier);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();               // see the other workgroups' writes
+}
+
+template <typename T>
+__device__ __forceinline__ T bias_correction(double beta, int64_t t)
+{
+    return (T)(1.0 - pow(beta, (double)t));
+}
+
+template <typename T, int D, int LANES, int VEC>
+__global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int c = blockIdx.x / F.W, w = blockIdx.x % F.W;
+    const FedClientDev<T>& C = F.clients[c];
+    const LGParams<T>& P = C.P;
+    T* M = const_cast<T*>(P.A);
+    T* G = P.G;
+    const int nwaves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint64_t* skey = reinterpret_cast<uint64_t*>(smem) + wave * 64;
+    T* sx = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * 8) + wave * 64;
+    T* sw = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * (8 + sizeof(T))) + wave * 64;
+    const int64_t round = *F.round;
+    const int64_t tid = (int64_t)w * blockDim.x + threadIdx.x;
+    const int64_t nthreads = (int64_t)F.W * blockDim.x;
+    int arrivals = 0;
+
+    // M_c <- the client's rows of the server model
+    for (int k = 0; k < F.d; ++k)
+        for (int64_t e = tid; e < C.seg_len[k]; e += nthreads) M[C.seg_dst[k] + e] = F.U[C.seg_src[k] + e];
+    fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+
+    for (int j = 0; j < F.tau; ++j) {
+        const uint64_t step = (uint64_t)(round * F.tau + j);
+        double lacc = 0.0;
+        for (int64_t chunk = (int64_t)w * nwaves + wave; chunk < P.nchunks; chunk += (int64_t)F.W * nwaves)
+            lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, nullptr, nullptr, nullptr, 0, false, T(1),
+                                          lacc, step);
+        fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+        const int64_t t = round * F.tau + j + 1;
+        const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
+        for (int64_t e = tid; e < C.nparams; e += nthreads) {
+            T p = M[e], b = C.B[e], cc = C.C[e];
+            adam_update<T>(p, G[e], b, cc, F.lr, F.b1, F.b2, F.one_m_b1, F.one_m_b2, c1, c2, F.eps, F.lower);
+            M[e] = p;
+            C.B[e] = b;
+            C.C[e] = cc;
+            G[e] = T(0);
+        }
+        if (j + 1 < F.tau) fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+    }
+}
+
+// Server step: D = per-row mean over covering clients of U - M_c, then Adam
+// on U with rate meta; also clears the clients' barrier counters.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fed_server(const FedArgs<T> F)
+{
+    const int64_t t = *F.round + 1;
+    const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = gid; e < F.nserver; e += stride) {
+        const int64_t row = e / F.R, col = e - row * F.R;
+        const int64_t b = F.cov_ptr[row], end = F.cov_ptr[row + 1];
+        T u = F.U[e];
+        T g = T(0);
+        for (int64_t i = b; i < end; ++i) g += u - F.Mptrs[F.cov_client[i]][(int64_t)F.cov_lrow[i] * F.R + col];
+        if (end > b) g /= T(end - b);
+        T bs = F.Bs[e], cs = F.Cs[e];
+        adam_update<T>(u, g, bs, cs, F.meta, F.b1, F.b2, F.one_m_b1, F.one_m_b2, c1, c2, F.eps, F.lower);
+        F.U[e] = u;
+        F.Bs[e] = bs;
+        F.Cs[e] = cs;
+    }
+    if (gid < F.K) F.barrier[gid] = 0;
+}
+
+// Per-client launches: M_c <- rows of U (blockIdx.y = client).
+template <typename T>
+__global__ void __launch_bounds__(256) k_fed_copy(const FedArgs<T> F)
+{
+    const FedClientDev<T>& C = F.clients[blockIdx.y];
+    T* M = const_cast<T*>(C.P.A);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)gridDim.x * blockDim.x;
+    for (int k = 0; k < F.d; ++k)
+        for (int64_t e = tid; e < C.seg_len[k]; e += n) M[C.seg_dst[k] + e] = F.U[C.seg_src[k] + e];
+}
+
+__global__ void k_fed_set_round(int64_t* round, int64_t value) { *round = value; }
+
+template <typename T>
+using FedKernel = void (*)(const FedArgs<T>);
+
+#define GCP_FED_SHAPES_F32(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(16, 2) X(32, 2) X(8, 4) X(16, 4)
+#define GCP_FED_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(16, 2) X(32, 2)
+
+template <typename T, int D>
+static FedKernel<T> pick_fed(int lanes, int vec)
+{
+#define GCP_CASE(LN, VC) \
+    if (lanes == LN && vec == VC) return k_fed_clients<T, D, LN, VC>;
+    if constexpr (sizeof(T) == 4) {
+        GCP_FED_SHAPES_F32(GCP_CASE)
+    } else {
+        GCP_FED_SHAPES_F64(GCP_CASE)
+    }
+#undef GCP_CASE
+    return nullptr;
+}
+
+}  // namespace gcp
+
+using namespace gcp;
+
+struct gcp_fed_s {
+    int device = 0;
+    gcp_dtype dt = GCP_F32;
+    gcp_fed_desc desc{};
+    std::vector<gcp_fed_client> clients;
+    int d = 0;
+    int W = 1, block = 256, lanes = 0, vec = 0;
+    int64_t nserver = 0;
+    void* dev_clients = nullptr;   // FedClientDev<T>[K]
+    void* dev_mptrs = nullptr;
+    int* barrier = nullptr;
+    int64_t* round = nullptr;
+    uint32_t* status = nullptr;
+    int64_t* cov_ptr = nullptr;
+    int* cov_client = nullptr;
+    int* cov_lrow = nullptr;
+    unsigned char args[sizeof(FedArgs<double>)] = {};   // FedArgs<T> for the tensor dtype
+    const void* client_kernel = nullptr;
+    size_t client_lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+namespace gcp {
+
+template <typename T>
+static gcp_status fed_build(gcp_fed_s* f)
+{
+    const gcp_fed_desc& D = f->desc;
+    const int K = D.nclients, R = D.R, d = f->d;
+    int64_t goff[kMaxModes + 1] = {0};
+    for (int k = 0; k < d; ++k) goff[k + 1] = goff[k] + D.global_dims[k];
+    f->nserver = goff[d] * R;
+    std::vector<FedClientDev<T>> host(K);
+    std::vector<T*> mptrs(K);
+    // coverage lists per server row
+    std::vector<int64_t> cnt(goff[d] + 1, 0);
+    for (int c = 0; c < K; ++c) {
+        const gcp_fed_client& cl = f->clients[c];
+        const gcp_tensor_s* t = cl.tensor;
+        for (int k = 0; k < d; ++k)
+            for (int64_t r = 0; r < t->dims[k]; ++r) cnt[goff[k] + cl.row_base[k] + r + 1]++;
+    }
+    for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+    std::vector<int64_t> ptr = cnt;
+    std::vector<int> cov_c(cnt.back()), cov_l(cnt.back());
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int c = 0; c < K; ++c) {
+        const gcp_fed_client& cl = f->clients[c];
+        const gcp_tensor_s* t = cl.tensor;
+        for (int k = 0; k < d; ++k)
+            for (int64_t r = 0; r < t->dims[k]; ++r) {
+                const int64_t g = goff[k] + cl.row_base[k] + r;
+                cov_c[fill[g]] = c;
+                cov_l[fill[g]] = (int)(t->rowoff[k] + r);
+                ++fill[g];
+            }
+    }
+    gcp_tile tile{};
+    tile.lanes = f->lanes;
+    tile.vec = f->vec;
+    tile.lds_modes = 0;
+    tile.bucket_modes = 0;
+    for (int c = 0; c < K; ++c) {
+        const gcp_fed_client& cl = f->clients[c];
+        const gcp_tensor_s* t = cl.tensor;
+        FedClientDev<T>& h = host[c];
+        gcp_sample_params sp{};
+        sp.kind = GCP_SAMPLE_STRATIFIED;
+        sp.max_attempts = D.max_attempts;
+        sp.p = D.p;
+        sp.q = D.q;
+        sp.seed = D.seed;
+        sp.step = 0;
+        sp.client = (uint64_t)c;
+        int64_t n = 0;
+        gcp_status st = make_sample_ctx<T>(t, &sp, h.P.sc, n);
+        if (st != GCP_OK) return st;
+        h.P.n = n;
+        h.P.nchunks = ceil_div(n, 64);
+        h.P.A = (const T*)cl.M;
+        h.P.G = (T*)cl.G;
+        h.P.R = R;
+        h.P.loss = D.loss;
+        for (int k = 0; k < kMaxModes; ++k) h.P.rowoff[k] = k < d ? t->rowoff[k] : t->rowoff[d];
+        for (int k = 0; k <= kMaxModes; ++k) h.P.bucket_base[k] = 0;
+        h.B = (T*)cl.B;
+        h.C = (T*)cl.C;
+        h.nparams = t->rowoff[d] * R;
+        for (int k = 0; k < kMaxModes; ++k) {
+            h.seg_src[k] = k < d ? (goff[k] + cl.row_base[k]) * R : 0;
+            h.seg_dst[k] = k < d ? t->rowoff[k] * R : 0;
+            h.seg_len[k] = k < d ? t->dims[k] * R : 0;
+        }
+        mptrs[c] = (T*)cl.M;
+    }
+    GCP_HIP(hipMalloc(&f->dev_clients, sizeof(FedClientDev<T>) * K));
+    GCP_HIP(hipMemcpy(f->dev_clients, host.data(), sizeof(FedClientDev<T>) * K, hipMemcpyHostToDevice));
+    GCP_HIP(hipMalloc(&f->dev_mptrs, sizeof(T*) * K));
+    GCP_HIP(hipMemcpy(f->dev_mptrs, mptrs.data(), sizeof(T*) * K, hipMemcpyHostToDevice));
+    GCP_HIP(hipMalloc((void**)&f->cov_ptr, sizeof(int64_t) * ptr.size()));
+    GCP_HIP(hipMemcpy(f->cov_ptr, ptr.data(), sizeof(int64_t) * ptr.size(), hipMemcpyHostToDevice));
+    const size_t ncov = std::max<size_t>(1, cov_c.size());
+    GCP_HIP(hipMalloc((void**)&f->cov_client, sizeof(int) * ncov));
+    GCP_HIP(hipMalloc((void**)&f->cov_lrow, sizeof(int) * ncov));
+    if (!cov_c.empty()) {
+        GCP_HIP(hipMemcpy(f->cov_client, cov_c.data(), sizeof(int) * cov_c.size(), hipMemcpyHostToDevice));
+        GCP_HIP(hipMemcpy(f->cov_lrow, cov_l.data(), sizeof(int) * cov_l.size(), hipMemcpyHostToDevice));
+    }
+    GCP_HIP(hipMalloc((void**)&f->barrier, sizeof(int) * K));
+    GCP_HIP(hipMemset(f->barrier, 0, sizeof(int) * K));
+    GCP_HIP(hipMalloc((void**)&f->round, sizeof(int64_t)));
+    GCP_HIP(hipMemset(f->round, 0, sizeof(int64_t)));
+    GCP_HIP(hipMalloc((void**)&f->status, sizeof(uint32_t)));
+    GCP_HIP(hipMemset(f->status, 0, sizeof(uint32_t)));
+
+    FedArgs<T> a{};
+    a.clients = (const FedClientDev<T>*)f->dev_clients;
+    a.K = K;
+    a.W = f->W;
+    a.tau = D.tau;
+    a.d = d;
+    a.R = R;
+    a.U = (T*)D.U;
+    a.Bs = (T*)D.Bs;
+    a.Cs = (T*)D.Cs;
+    a.nserver = f->nserver;
+    a.lr = (T)D.lr;
+    a.meta = (T)D.meta_lr;
+    a.b1 = (T)D.beta1;
+    a.b2 = (T)D.beta2;
+    a.one_m_b1 = (T)(1.0 - D.beta1);
+    a.one_m_b2 = (T)(1.0 - D.beta2);
+    a.eps = (T)D.eps;
+    a.lower = (T)D.lower;
+    a.b1d = D.beta1;
+    a.b2d = D.beta2;
+    a.barrier = f->barrier;
+    a.round = f->round;
+    a.status = f->status;
+    a.cov_ptr = f->cov_ptr;
+    a.cov_client = f->cov_client;
+    a.cov_lrow = f->cov_lrow;
+    a.Mptrs = (T* const*)f->dev_mptrs;
+    memcpy(f->args, &a, sizeof(a));
+
+    if (D.batched) {
+        FedKernel<T> kern = nullptr;
+        if (d == 3) kern = pick_fed<T, 3>(f->lanes, f->vec);
+        else kern = pick_fed<T, 0>(f->lanes, f->vec);
+        if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "batched lane shape lanes = %d, vec = %d not built", f->lanes,
+                                    f->vec);
+        f->client_kernel = reinterpret_cast<const void*>(kern);
+        f->client_lds = (size_t)(f->block / 64) * 64 * (8 + 2 * sizeof(T));
+        int per_cu = 0;
+        GCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f->client_kernel, f->block, f->client_lds));
+        const int64_t resident = (int64_t)per_cu * device_cu_count(f->device);
+        if ((int64_t)K * f->W > resident)
+            return set_error(GCP_ERR_UNSUPPORTED,
+                             "%d clients x %d workgroups exceed the %lld workgroups the GPU holds at once", K, f->W,
+                             (long long)resident);
+    }
+    return GCP_OK;
+}
+
+template <typename T>
+static gcp_status fed_launch_batched(gcp_fed_s* f, hipStream_t stream)
+{
+    const FedArgs<T>& a = *reinterpret_cast<const FedArgs<T>*>(f->args);
+    hipLaunchKernelGGL(reinterpret_cast<FedKernel<T>>(const_cast<void*>(f->client_kernel)),
+                       dim3((unsigned)(f->desc.nclients * f->W)), dim3(f->block), f->client_lds, stream, a);
+    GCP_HIP(hipGetLastError());
+    const int64_t sb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(f->nserver, 256), 2048));
+    k_fed_server<T><<<(unsigned)sb, 256, 0, stream>>>(a);
+    GCP_HIP(hipGetLastError());
+    return GCP_OK;
+}
+
+template <typename T>
+static gcp_status fed_round_plain(gcp_fed_s* f, int64_t round, hipStream_t stream)
+{
+    const FedArgs<T>& a = *reinterpret_cast<const FedArgs<T>*>(f->args);
+    const gcp_fed_desc& D = f->desc;
+    int64_t maxlen = 0;
+    for (const gcp_fed_client& cl : f->clients) maxlen = std::max<int64_t>(maxlen, cl.tensor->rowoff[f->d] * D.R);
+    const unsigned cb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(maxlen, 256), 1024));
+    k_fed_copy<T><<<dim3(cb, (unsigned)D.nclients), 256, 0, stream>>>(a);
+    GCP_HIP(hipGetLastError());
+    gcp_tile tile{};
+    tile.lanes = f->lanes;
+    tile.vec = f->vec;
+    tile.lds_modes = 0;
+    tile.bucket_modes = 0;
+    for (int j = 0; j < D.tau; ++j) {
+        for (int c = 0; c < D.nclients; ++c) {
+            const gcp_fed_client& cl = f->clients[c];
+            gcp_sample_params sp{};
+            sp.kind = GCP_SAMPLE_STRATIFIED;
+            sp.max_attempts = D.max_attempts;
+            sp.p = D.p;
+            sp.q = D.q;
+            sp.seed = D.seed;
+            sp.step = (uint64_t)(round * D.tau + j);
+            sp.client = (uint64_t)c;
+            gcp_status st = gcp_loss_grad(cl.tensor, &sp, nullptr, cl.M, D.R, (gcp_loss)D.loss, GCP_ACCUMULATE,
+                                          nullptr, cl.G, nullptr, &tile, stream);
+            if (st != GCP_OK) return st;
+            st = gcp_adam_step(cl.M, cl.G, cl.B, cl.C, cl.tensor->rowoff[f->d] * D.R, f->dt, round * D.tau + j + 1,
+                               D.lr, D.beta1, D.beta2, D.eps, D.lower, GCP_ADAM_ZERO_GRAD, stream);
+            if (st != GCP_OK) return st;
+        }
+    }
+    const int64_t sb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(f->nserver, 256), 2048));
+    k_fed_server<T><<<(unsigned)sb, 256, 0, stream>>>(a);
+    GCP_HIP(hipGetLastError());
+    return GCP_OK;
+}
+
+static void fed_free(gcp_fed_s* f)
+{
+    if (!f) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(f->device);
+    (void)hipDeviceSynchronize();
+    if (f->exec) (void)hipGraphExecDestroy(f->exec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
+    void* ptrs[] = {f->dev_clients, f->dev_mptrs, f->barrier, f->round, f->status, f->cov_ptr, f->cov_client,
+                    f->cov_lrow};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    (void)hipSetDevice(cur);
+    delete f;
+}
+
+}  // namespace gcp
+
+extern "C" {
+
+gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_t stream)
+{
+    clear_error();
+    (void)stream;
+    if (!out || !desc) return set_error(GCP_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    const gcp_fed_desc& D = *desc;
+    if (D.nclients < 1 || !D.clients) return set_error(GCP_ERR_ARG, "no clients");
+    if (D.R < 1 || D.R > 256) return set_error(GCP_ERR_ARG, "R = %d outside [1, 256]", D.R);
+    if (D.tau < 1) return set_error(GCP_ERR_ARG, "tau = %d < 1", D.tau);
+    if (D.loss < GCP_LOSS_GAUSSIAN || D.loss > GCP_LOSS_BERNOULLI_LOGIT) return set_error(GCP_ERR_ARG, "loss");
+    if (D.p < 0 || D.q < 0) return set_error(GCP_ERR_ARG, "negative sample count");
+    if (!D.U || !D.Bs || !D.Cs) return set_error(GCP_ERR_ARG, "server buffers are NULL");
+    if (!(D.beta1 >= 0 && D.beta1 < 1) || !(D.beta2 >= 0 && D.beta2 < 1) || !(D.eps >= 0))
+        return set_error(GCP_ERR_ARG, "Adam constants");
+    gcp_fed_s* f = new (std::nothrow) gcp_fed_s();
+    if (!f) return set_error(GCP_ERR_OOM, "host allocation");
+    f->desc = D;
+    f->clients.assign(D.clients, D.clients + D.nclients);
+    f->desc.clients = nullptr;
+    (void)hipGetDevice(&f->device);
+    const gcp_tensor_s* t0 = D.clients[0].tensor;
+    if (!t0) { delete f; return set_error(GCP_ERR_ARG, "client 0 has no tensor"); }
+    f->dt = t0->dt;
+    f->d = t0->d;
+    for (int c = 0; c < D.nclients; ++c) {
+        const gcp_fed_client& cl = D.clients[c];
+        const gcp_tensor_s* t = cl.tensor;
+        if (!t || t->dense || t->dt != f->dt || t->d != f->d) {
+            delete f;
+            return set_error(GCP_ERR_ARG, "client %d: tensor missing, dense, or of another dtype or order", c);
+        }
+        if (!cl.M || !cl.B || !cl.C || !cl.G) { delete f; return set_error(GCP_ERR_ARG, "client %d: NULL buffer", c); }
+        if (D.q > 0 && t->nnz >= t->cells) {
+            delete f;
+            return set_error(GCP_ERR_ARG, "client %d: q > 0 but the block has no zero cells", c);
+        }
+        for (int k = 0; k < f->d; ++k) {
+            if (cl.row_base[k] < 0 || cl.row_base[k] + t->dims[k] > D.global_dims[k]) {
+                delete f;
+                return set_error(GCP_ERR_ARG, "client %d: block outside the global dims in mode %d", c, k);
+            }
+        }
+    }
+    const int esize = f->dt == GCP_F32 ? 4 : 8;
+    f->block = D.block > 0 ? D.block : 256;
+    if (f->block % 64 != 0 || f->block > 1024) { delete f; return set_error(GCP_ERR_ARG, "block = %d", f->block); }
+    // lane shape: one column per lane up to R = 64 (coalesced gradient atomics)
+    f->vec = D.vec > 0 ? D.vec : (D.R > 64 && D.R % 2 == 0 ? 2 : 1);
+    if (D.lanes > 0) f->lanes = D.lanes;
+    else {
+        const int need = (D.R + f->vec - 1) / f->vec;
+        f->lanes = 8;
+        while (f->lanes < need && f->lanes < 64) f->lanes <<= 1;
+    }
+    if (D.R % f->vec != 0 || f->lanes * f->vec < D.R) {
+        delete f;
+        return set_error(GCP_ERR_ARG, "lane shape %d x %d does not cover R = %d", f->lanes, f->vec, D.R);
+    }
+    if (D.batched) {
+        if (D.workgroups_per_client > 0) f->W = D.workgroups_per_client;
+        else {
+            // fill the GPU with resident workgroups, at most 16 per client
+            const int cus = device_cu_count(f->device);
+            const int per_cu = std::max(1, 2048 / f->block);     // waves per CU budget of 32
+            f->W = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)cus * per_cu / 2 / D.nclients));
+        }
+    }
+    (void)esize;
+    gcp_status st = f->dt == GCP_F32 ? fed_build<float>(f) : fed_build<double>(f);
+    if (st != GCP_OK) {
+        fed_free(f);
+        return st;
+    }
+    *out = f;
+    return GCP_OK;
+}
+
+gcp_status gcp_fedadam_round(gcp_fed f, int64_t round, hipStream_t stream)
+{
+    clear_error();
+    if (!f) return set_error(GCP_ERR_ARG, "handle is NULL");
+    if (round < 0) return set_error(GCP_ERR_ARG, "round < 0");
+    k_fed_set_round<<<1, 1, 0, stream>>>(f->round, round);
+    GCP_HIP(hipGetLastError());
+    if (!f->desc.batched) return f->dt == GCP_F32 ? fed_round_plain<float>(f, round, stream)
+                                                  : fed_round_plain<double>(f, round, stream);
+    if (!f->desc.use_graph)
+        return f->dt == GCP_F32 ? fed_launch_batched<float>(f, stream) : fed_launch_batched<double>(f, stream);
+    if (!stream) return set_error(GCP_ERR_ARG, "use_graph needs a non-default stream");
+    if (f->exec && f->graph_stream != stream) return set_error(GCP_ERR_ARG, "the graph was captured on another stream");
+    if (!f->exec) {
+        GCP_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        gcp_status st = f->dt == GCP_F32 ? fed_launch_batched<float>(f, stream) : fed_launch_batched<double>(f, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &g);
+        if (st != GCP_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&f->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            f->exec = nullptr;
+            return hip_error(e, "hipGraphInstantiate");
+        }
+        f->graph = g;
+        f->graph_stream = stream;
+    }
+    GCP_HIP(hipGraphLaunch(f->exec, stream));
+    return GCP_OK;
+}
+
+gcp_status gcp_fedadam_status(gcp_fed f, hipStream_t stream)
+{
+    clear_error();
+    if (!f) return set_error(GCP_ERR_ARG, "handle is NULL");
+    GCP_HIP(hipStreamSynchronize(stream));
+    uint32_t hs = 0;
+    GCP_HIP(hipMemcpy(&hs, f->status, sizeof(hs), hipMemcpyDeviceToHost));
+    if (hs) GCP_HIP(hipMemset(f->status, 0, sizeof(uint32_t)));
+    gcp_status worst = GCP_OK;
+    for (const gcp_fed_client& cl : f->clients) {
+        gcp_status st = gcp_device_status(cl.tensor, stream);
+        if (st != GCP_OK) worst = st;
+    }
+    if (hs & kStatusBarrier)
+        return set_error(GCP_ERR_HIP, "a batched round's group barrier timed out (workgroups not co-resident)");
+    if (worst != GCP_OK) return set_error(worst, "a client tensor reported a device error");
+    return GCP_OK;
+}
+
+int64_t gcp_struct_size(const char* name)
+{
+    if (!name) return -1;
+    if (!strcmp(name, "gcp_sample_params")) return sizeof(gcp_sample_params);
+    if (!strcmp(name, "gcp_samples")) return sizeof(gcp_samples);
+    if (!strcmp(name, "gcp_tile")) return sizeof(gcp_tile);
+    if (!strcmp(name, "gcp_fed_client")) return sizeof(gcp_fed_client);
+    if (!strcmp(name, "gcp_fed_desc")) return sizeof(gcp_fed_desc);
+    return -1;
+}
+
+gcp_status gcp_fedadam_destroy(gcp_fed f)
+{
+    clear_error();
+    if (!f) return set_error(GCP_ERR_ARG, "handle is NULL");
+    fed_free(f);
+    return GCP_OK;
+}
+
+}  // extern "C"

@@ -68,6 +68,12 @@ struct gcp_tensor_s {
     const void* dense_vals = nullptr;  // dense: borrowed values
     uint32_t* status = nullptr;        // device status word
     int64_t owned_bytes = 0;
+    // workspace of the bucketed scatter (gcp_tensor_reserve)
+    void* ws = nullptr;
+    int64_t ws_entries = 0;            // 16-byte sample entries
+    int64_t ws_hist = 0;               // ints in each of the count and start arrays
+    int64_t ws_bytes = 0;
+    int64_t ws_max_samples = 0;        // samples per call the workspace was sized for
 };
 
 namespace gcp {
@@ -212,9 +218,25 @@ __device__ __forceinline__ T loss_f(int loss, T x, T m)
     return (m > T(0) ? m : T(0)) + log1p(exp(-fabs(m))) - x * m;
 }
 
+// ------------------------------------------------------------------- Adam --
+// One element of Alg. adam-update; c1 = 1 - beta1^t and c2 = 1 - beta2^t.
+template <typename T>
+__device__ __forceinline__ void adam_update(T& p, T g, T& b, T& c, T lr, T b1, T b2, T one_m_b1, T one_m_b2, T c1,
+                                            T c2, T eps, T lower)
+{
+    b = b1 * b + one_m_b1 * g;
+    c = b2 * c + one_m_b2 * g * g;
+    const T bhat = b / c1;
+    const T chat = c / c2;
+    p = fmax(p - lr * (bhat / sqrt(chat + eps)), lower);
+}
+
 // -------------------------------------------------------------- host misc --
 
 int device_cu_count(int device);
 int64_t ceil_div(int64_t a, int64_t b);
+// Checks a launch's dynamic LDS against the device limit and opts the kernel
+// in to more than 64 KiB when needed.
+gcp_status prepare_lds(const void* fn, size_t bytes, int device);
 
 }  // namespace gcp

@@ -1,0 +1,278 @@
+// Device core of the fused sampled loss/gradient: kernel parameters, small
+// helpers and the per-chunk body shared by the HIP kernels.
+#pragma once
+
+#include <algorithm>
+
+#include "sampling.hpp"
+
+namespace gcp {
+
+template <typename T>
+struct LGParams {
+    SampleCtx<T> sc;
+    int64_t n;            // samples p + q
+    int64_t nchunks;      // ceil(n / 64)
+    const int64_t* m_coords;  // materialised list (SRC = 1)
+    const T* m_x;
+    const T* m_w;
+    const T* A;
+    T* G;
+    int R;
+    int loss;
+    int loss_only;
+    int semi;             // semi-stratified: samples s < p get f'(x,m) - f'(0,m)
+    const T* scale;       // nullable device scalar
+    double* loss_out;     // nullable
+    int64_t rowoff[kMaxModes];
+    uint32_t lds_mask;    // modes accumulated in LDS
+    int64_t lds_off[kMaxModes];
+    int64_t lds_elems;
+    int staging_bytes;
+    // bucketed scatter
+    uint32_t bucket_mask;      // modes scattered through row-block buckets
+    int n_bucket_modes;
+    int br_shift;              // rows per bucket = 1 << br_shift
+    int nb;                    // buckets over all bucketed modes
+    int bucket_base[kMaxModes + 1];
+    int spb;                   // samples per workgroup (tiled launch)
+    int64_t nblocks;           // workgroups of the tiled launch (J)
+    int64_t entry_cap;         // entries per workgroup segment list = spb * n_bucket_modes
+    int bucket_lds;            // byte offset of the bucket staging in LDS
+    uint4* entries;            // [J][entry_cap] 16-byte {key, y}
+    int* hist;                 // [nb][J] entries per (bucket, workgroup)
+    int* start;                // [nb][J] first entry of the bucket in the workgroup's list
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&out)[V])
+{
+    if constexpr (V == 4 && sizeof(T) == 4) {
+        float4 f = *reinterpret_cast<const float4*>(p);
+        out[0] = f.x; out[1] = f.y; out[2] = f.z; out[3] = f.w;
+    } else if constexpr (V == 2 && sizeof(T) == 4) {
+        float2 f = *reinterpret_cast<const float2*>(p);
+        out[0] = f.x; out[1] = f.y;
+    } else if constexpr (V == 2 && sizeof(T) == 8) {
+        double2 f = *reinterpret_cast<const double2*>(p);
+        out[0] = f.x; out[1] = f.y;
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = p[v];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void global_add(T* p, T v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+template <typename T>
+__device__ __forceinline__ uint4 pack_entry(uint64_t key, T y)
+{
+    uint4 e;
+    e.x = (uint32_t)key;
+    e.y = (uint32_t)(key >> 32);
+    if constexpr (sizeof(T) == 4) {
+        e.z = __float_as_uint(y);
+        e.w = 0;
+    } else {
+        const uint64_t b = (uint64_t)__double_as_longlong(y);
+        e.z = (uint32_t)b;
+        e.w = (uint32_t)(b >> 32);
+    }
+    return e;
+}
+
+template <typename T>
+__device__ __forceinline__ T entry_y(uint4 e)
+{
+    if constexpr (sizeof(T) == 4) return __uint_as_float(e.z);
+    else return __longlong_as_double((long long)(((uint64_t)e.w << 32) | e.z));
+}
+
+// Butterfly exchange across lanes (lane ^ mask).  Doubles move as two 32-bit
+// halves: the 64-bit form of the cross-half exchange trips a gfx950 code
+// generation error in this toolchain.
+__device__ __forceinline__ float xor_shfl(float v, int mask) { return __shfl_xor(v, mask, 64); }
+__device__ __forceinline__ double xor_shfl(double v, int mask)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __shfl_xor((int)(b & 0xffffffffll), mask, 64);
+    const int hi = __shfl_xor((int)(b >> 32), mask, 64);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Exclusive prefix sum of cnt[0, n) into off[0, n) by one wavefront.
+__device__ inline void wave_exclusive_scan(const int* cnt, int* off, int n, int lane)
+{
+    const int per = (n + 63) / 64;
+    const int b0 = lane * per;
+    int local = 0;
+    for (int i = 0; i < per; ++i)
+        if (b0 + i < n) local += cnt[b0 + i];
+    int incl = local;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    int run = incl - local;
+    for (int i = 0; i < per; ++i) {
+        if (b0 + i < n) {
+            off[b0 + i] = run;
+            run += cnt[b0 + i];
+        }
+    }
+}
+
+// One chunk of 64 samples: phase 1 (one lane per sample: draw or read the
+// sample, stage it in the wave's LDS slice) and phase 2 (LANES lanes per
+// sample: gather rows, model value, loss derivative, scatter).  Shared by the
+// sampled-gradient kernel and the batched GCP-FedAdam kernel.
+template <typename T, int D, int LANES, int VEC, int SRC>
+__device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, int lane, uint64_t* skey, T* sx,
+                                         T* sw, T* priv, uint64_t* bkey, T* by, int64_t block_s0, bool tiled,
+                                         T scale, double& lacc, uint64_t step)
+{
+    constexpr int S = 64 / LANES;                  // samples per pass
+    // samples per lane group whose row gathers are issued together
+    constexpr int U = (D == 0 || LANES < 4) ? 1 : (sizeof(T) == 4 ? 4 : 2);
+    constexpr int DM = D > 0 ? D : kMaxModes;
+    const int dd = D > 0 ? D : P.sc.d;
+    const int R = P.R;
+    const int g = lane / LANES, cl = lane % LANES;
+    const int col0 = cl * VEC;
+    const bool col_ok = col0 < R;          // VEC divides R
+    const int64_t s0 = chunk * 64;
+    {   // phase 1: one lane per sample
+        const int64_t s = s0 + lane;
+        uint64_t key = 0;
+        T x = T(0), w = T(0);
+        if (s < P.n) {
+            if constexpr (SRC == 0) {
+                draw_sample<T, D>(P.sc, step, s, key, x, w);
+            } else {
+                bool ok = true;
+#pragma unroll
+                for (int k = 0; k < DM; ++k) {
+                    if (k < dd) {
+                        int64_t c = P.m_coords[s * dd + k];
+                        if (c < 0 || c >= P.sc.L.dims[k]) ok = false;
+                        else key |= (uint64_t)c << P.sc.L.shift[k];
+                    }
+                }
+                x = P.m_x[s];
+                w = P.m_w[s];
+                if (!ok) {
+                    atomicOr(P.sc.status, kStatusData);
+                    key = 0;
+                    w = T(0);
+                }
+            }
+        }
+        skey[lane] = key;
+        sx[lane] = x;
+        sw[lane] = w;
+    }
+    wave_sync();
+    // phase 2: LANES lanes per sample, U samples per lane group in flight
+    for (int it = 0; it < LANES; it += U) {
+        uint64_t key[U];
+        T a[U][DM][VEC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int slot = (it + u) * S + g;
+            const bool valid = s0 + slot < P.n;
+            key[u] = skey[slot];
+#pragma unroll
+            for (int k = 0; k < DM; ++k) {
+                if (k < dd) {
+                    const int64_t row = P.rowoff[k] + (int64_t)unpack(P.sc.L, key[u], k);
+                    if (col_ok && valid) {
+                        load_cols<T, VEC>(P.A + row * R + col0, a[u][k]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) a[u][k][v] = T(0);
+                    }
+                }
+            }
+        }
+        T m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            T part = T(0);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                T prod = a[u][0][v];
+#pragma unroll
+                for (int k = 1; k < DM; ++k)
+                    if (k < dd) prod *= a[u][k][v];
+                part += prod;
+            }
+            m[u] = part;
+        }
+#pragma unroll
+        for (int off = LANES / 2; off >= 1; off >>= 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) m[u] += xor_shfl(m[u], off);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int slot = (it + u) * S + g;
+            const int64_t s = s0 + slot;
+            if (s >= P.n) continue;
+            const T x = sx[slot], w = sw[slot];
+            const bool semi_nz = P.semi && s < P.sc.p;
+            T y = w * loss_df<T>(P.loss, x, m[u]);
+            if (semi_nz) y -= w * loss_df<T>(P.loss, T(0), m[u]);
+            if (P.loss_out && cl == 0) {
+                T l = w * loss_f<T>(P.loss, x, m[u]);
+                if (semi_nz) l -= w * loss_f<T>(P.loss, T(0), m[u]);
+                lacc += (double)l;
+            }
+            if (P.loss_only) continue;
+            y *= scale;
+            if (tiled && cl == 0) {
+                bkey[s - block_s0] = key[u];
+                by[s - block_s0] = y;
+            }
+            if (!col_ok) continue;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                // leave-one-out products by prefix and suffix running products
+                T pre[DM];
+                pre[0] = y;
+#pragma unroll
+                for (int k = 1; k < DM; ++k)
+                    if (k < dd) pre[k] = pre[k - 1] * a[u][k - 1][v];
+                T suf = T(1);
+#pragma unroll
+                for (int k = DM - 1; k >= 0; --k) {
+                    if (k < dd) {
+                        const T c = pre[k] * suf;
+                        suf *= a[u][k][v];
+                        if ((P.bucket_mask >> k) & 1u) continue;
+                        const int64_t i = (int64_t)unpack(P.sc.L, key[u], k);
+                        if ((P.lds_mask >> k) & 1u) {
+                            atomicAdd(priv + P.lds_off[k] + i * R + col0 + v, c);
+                        } else {
+                            global_add(P.G + (P.rowoff[k] + i) * R + col0 + v, c);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+}  // namespace gcp

@@ -2,84 +2,38 @@
 // "Fused Sampling-MTTKRP", here with stratified, uniform or semi-stratified
 // samples).
 //
-// Work decomposition (one 64-lane wavefront takes 64 samples at a time):
+// Work decomposition of k_loss_grad (one 64-lane wavefront takes 64 samples
+// at a time):
 //   phase 1, one lane per sample: draw the sample (Philox, nonzero record
 //     read or zero-candidate hash probes) or read it from a materialised
 //     list, and stage (packed key, x, w) in the wave's LDS slice;
 //   phase 2, LANES lanes per sample with VEC consecutive columns each, 64 /
-//     LANES samples per pass: gather the d factor rows (coalesced LANES*VEC
-//     columns), m = sum_r prod_k A_k[i_k, r] (eq. cp) by a butterfly over
-//     the lane group, y = w f'(x, m), then the leave-one-out products
-//     y prod_{n != k} A_n[i_n, r] are added into G_k[i_k, :] with hardware
-//     float atomics -- into global memory, or into an LDS-private copy of a
-//     small mode's gradient that the workgroup flushes once at the end (the
-//     paper's "thread privatization", per workgroup).
+//     LANES samples per pass and U samples per lane group in flight: gather
+//     the d factor rows, m = sum_r prod_k A_k[i_k, r] (eq. cp) by a butterfly
+//     over the lane group, y = w f'(x, m), then scatter the leave-one-out
+//     products y prod_{n != k} A_n[i_n, r] into G_k[i_k, :].
 // Factor rows are read once per sample and the sampled tensor is never
-// written to memory.
-#include <algorithm>
-
-#include "sampling.hpp"
+// written to memory.  Three scatter strategies, chosen per mode (the paper's
+// MTTKRP variants, Sec. 3.1.2):
+//   * atomic: hardware float atomics straight into G (one 128-byte request
+//     per row and sample);
+//   * LDS-private: a small mode's whole gradient lives in each workgroup's
+//     LDS and is flushed once ("thread privatization" per workgroup);
+//   * bucketed (sort-by-row): each workgroup sorts its samples' (key, y) by
+//     row block of the mode into a per-workgroup segment list in global
+//     memory; k_bucket_accum then gives every row block to its own
+//     workgroups, which re-gather the other modes' rows, accumulate the
+//     block in LDS and flush it once.  This replaces d atomic requests per
+//     sample by one 16-byte entry write and read per mode -- hardware float
+//     atomics are executed beyond the L2 at a fixed request rate, which
+//     bounds the atomic strategy at large sample counts.
+#include "lg_core.hpp"
 
 namespace gcp {
-
-template <typename T>
-struct LGParams {
-    SampleCtx<T> sc;
-    int64_t n;            // samples p + q
-    int64_t nchunks;      // ceil(n / 64)
-    const int64_t* m_coords;  // materialised list (SRC = 1)
-    const T* m_x;
-    const T* m_w;
-    const T* A;
-    T* G;
-    int R;
-    int loss;
-    int loss_only;
-    int semi;             // semi-stratified: samples s < p get f'(x,m) - f'(0,m)
-    const T* scale;       // nullable device scalar
-    double* loss_out;     // nullable
-    int64_t rowoff[kMaxModes];
-    uint32_t lds_mask;    // modes accumulated in LDS
-    int64_t lds_off[kMaxModes];
-    int64_t lds_elems;
-    int staging_bytes;
-};
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T, int V>
-__device__ __forceinline__ void load_cols(const T* __restrict__ p, T (&out)[V])
-{
-    if constexpr (V == 4 && sizeof(T) == 4) {
-        float4 f = *reinterpret_cast<const float4*>(p);
-        out[0] = f.x; out[1] = f.y; out[2] = f.z; out[3] = f.w;
-    } else if constexpr (V == 2 && sizeof(T) == 4) {
-        float2 f = *reinterpret_cast<const float2*>(p);
-        out[0] = f.x; out[1] = f.y;
-    } else if constexpr (V == 2 && sizeof(T) == 8) {
-        double2 f = *reinterpret_cast<const double2*>(p);
-        out[0] = f.x; out[1] = f.y;
-    } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) out[v] = p[v];
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void global_add(T* p, T v)
-{
-    unsafeAtomicAdd(p, v);
-}
 
 template <typename T, int D, int LANES, int VEC, int SRC>
 __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
 {
-    constexpr int S = 64 / LANES;                  // samples per pass
     constexpr int DM = D > 0 ? D : kMaxModes;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int nwaves = blockDim.x >> 6;
@@ -88,6 +42,11 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
     T* sx = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * 8) + wave * 64;
     T* sw = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * (8 + sizeof(T))) + wave * 64;
     T* priv = reinterpret_cast<T*>(smem + P.staging_bytes);
+    // bucketed scatter staging: the workgroup's samples in order
+    uint64_t* bkey = reinterpret_cast<uint64_t*>(smem + P.bucket_lds);
+    T* by = reinterpret_cast<T*>(smem + P.bucket_lds + (size_t)P.spb * 8);
+    int* bcnt = reinterpret_cast<int*>(smem + P.bucket_lds + (size_t)P.spb * (8 + sizeof(T)));
+    int* boff = bcnt + P.nb;
 
     if (P.lds_mask) {
         for (int64_t e = threadIdx.x; e < P.lds_elems; e += blockDim.x) priv[e] = T(0);
@@ -95,117 +54,30 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
     }
     const int dd = D > 0 ? D : P.sc.d;
     const int R = P.R;
-    const int g = lane / LANES, cl = lane % LANES;
-    const int col0 = cl * VEC;
-    const bool col_ok = col0 < R;          // VEC divides R
     const T scale = P.scale ? *P.scale : T(1);
+    const bool tiled = P.bucket_mask != 0;
+    const int64_t block_s0 = tiled ? (int64_t)blockIdx.x * P.spb : 0;
     double lacc = 0.0;
 
-    for (int64_t chunk = (int64_t)blockIdx.x * nwaves + wave; chunk < P.nchunks;
-         chunk += (int64_t)gridDim.x * nwaves) {
-        const int64_t s0 = chunk * 64;
-        {   // phase 1: one lane per sample
-            const int64_t s = s0 + lane;
-            uint64_t key = 0;
-            T x = T(0), w = T(0);
-            if (s < P.n) {
-                if constexpr (SRC == 0) {
-                    draw_sample<T, D>(P.sc, s, key, x, w);
-                } else {
-                    bool ok = true;
-#pragma unroll
-                    for (int k = 0; k < DM; ++k) {
-                        if (k < dd) {
-                            int64_t c = P.m_coords[s * dd + k];
-                            if (c < 0 || c >= P.sc.L.dims[k]) ok = false;
-                            else key |= (uint64_t)c << P.sc.L.shift[k];
-                        }
-                    }
-                    x = P.m_x[s];
-                    w = P.m_w[s];
-                    if (!ok) {
-                        atomicOr(P.sc.status, kStatusData);
-                        key = 0;
-                        w = T(0);
-                    }
-                }
-            }
-            skey[lane] = key;
-            sx[lane] = x;
-            sw[lane] = w;
-        }
-        wave_sync();
-        // phase 2: LANES lanes per sample
-        for (int it = 0; it < LANES; ++it) {
-            const int slot = it * S + g;
-            const int64_t s = s0 + slot;
-            if (s >= P.n) break;
-            const uint64_t key = skey[slot];
-            const T x = sx[slot], w = sw[slot];
-            int64_t row[DM];
-            T a[DM][VEC];
-#pragma unroll
-            for (int k = 0; k < DM; ++k) {
-                if (k < dd) {
-                    row[k] = P.rowoff[k] + (int64_t)unpack(P.sc.L, key, k);
-                    if (col_ok) {
-                        load_cols<T, VEC>(P.A + row[k] * R + col0, a[k]);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < VEC; ++v) a[k][v] = T(0);
-                    }
-                }
-            }
-            T part = T(0);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                T prod = a[0][v];
-#pragma unroll
-                for (int k = 1; k < DM; ++k)
-                    if (k < dd) prod *= a[k][v];
-                part += prod;
-            }
-#pragma unroll
-            for (int off = LANES / 2; off >= 1; off >>= 1) part += __shfl_xor(part, off, 64);
-            const T m = part;
-            const bool semi_nz = P.semi && s < P.sc.p;
-            T y = w * loss_df<T>(P.loss, x, m);
-            if (semi_nz) y -= w * loss_df<T>(P.loss, T(0), m);
-            if (P.loss_out && cl == 0) {
-                T l = w * loss_f<T>(P.loss, x, m);
-                if (semi_nz) l -= w * loss_f<T>(P.loss, T(0), m);
-                lacc += (double)l;
-            }
-            if (P.loss_only || !col_ok) continue;
-            y *= scale;
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                // leave-one-out products by prefix and suffix running products
-                T pre[DM];
-                pre[0] = y;
-#pragma unroll
-                for (int k = 1; k < DM; ++k)
-                    if (k < dd) pre[k] = pre[k - 1] * a[k - 1][v];
-                T suf = T(1);
-#pragma unroll
-                for (int k = DM - 1; k >= 0; --k) {
-                    if (k < dd) {
-                        const T c = pre[k] * suf;
-                        suf *= a[k][v];
-                        if ((P.lds_mask >> k) & 1u) {
-                            atomicAdd(priv + P.lds_off[k] + (row[k] - P.rowoff[k]) * R + col0 + v, c);
-                        } else {
-                            global_add(P.G + row[k] * R + col0 + v, c);
-                        }
-                    }
-                }
-            }
-        }
-        wave_sync();
+    // tiled launches give workgroup j the chunks of samples [j*spb, (j+1)*spb)
+    int64_t chunk, chunk_end, chunk_step;
+    if (tiled) {
+        chunk = block_s0 / 64 + wave;
+        chunk_end = std::min<int64_t>(P.nchunks, (block_s0 + P.spb) / 64);
+        chunk_step = nwaves;
+    } else {
+        chunk = (int64_t)blockIdx.x * nwaves + wave;
+        chunk_end = P.nchunks;
+        chunk_step = (int64_t)gridDim.x * nwaves;
+    }
+
+    for (; chunk < chunk_end; chunk += chunk_step) {
+        lg_chunk<T, D, LANES, VEC, SRC>(P, chunk, lane, skey, sx, sw, priv, bkey, by, block_s0, tiled, scale,
+                                        lacc, P.sc.step);
     }
 
     if (P.loss_out) {
-        for (int off = 32; off >= 1; off >>= 1) lacc += __shfl_xor(lacc, off, 64);
+        for (int off = 32; off >= 1; off >>= 1) lacc += xor_shfl(lacc, off);
         if (lane == 0 && lacc != 0.0) atomicAdd(P.loss_out, lacc);
     }
     if (P.lds_mask) {
@@ -223,6 +95,128 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
             }
         }
     }
+    if (tiled && !P.loss_only) {
+        // sort this workgroup's samples by (mode, row block) into its
+        // segment list: count, scan, place
+        __syncthreads();
+        const int nvalid = (int)std::min<int64_t>(P.spb, P.n - block_s0);
+        for (int b = threadIdx.x; b < P.nb; b += blockDim.x) bcnt[b] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            if (k < dd && ((P.bucket_mask >> k) & 1u)) {
+                for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
+                    const int b = P.bucket_base[k] + (int)(unpack(P.sc.L, bkey[e], k) >> P.br_shift);
+                    atomicAdd(bcnt + b, 1);
+                }
+            }
+        }
+        __syncthreads();
+        if (wave == 0) wave_exclusive_scan(bcnt, boff, P.nb, lane);
+        __syncthreads();
+        for (int b = threadIdx.x; b < P.nb; b += blockDim.x) {
+            P.hist[(int64_t)b * P.nblocks + blockIdx.x] = bcnt[b];
+            P.start[(int64_t)b * P.nblocks + blockIdx.x] = boff[b];
+        }
+        __syncthreads();
+        uint4* seg = P.entries + (int64_t)blockIdx.x * P.entry_cap;
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            if (k < dd && ((P.bucket_mask >> k) & 1u)) {
+                for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
+                    const uint64_t key = bkey[e];
+                    const int b = P.bucket_base[k] + (int)(unpack(P.sc.L, key, k) >> P.br_shift);
+                    const int pos = atomicAdd(boff + b, 1);
+                    seg[pos] = pack_entry<T>(key, by[e]);
+                }
+            }
+        }
+    }
+}
+
+// Row-block owner pass of the bucketed scatter.  Workgroup (b, split) owns
+// rows [r0, r0 + 2^br_shift) of bucket b's mode k and reads the segments of
+// workgroups [j0, j1) of the sampling launch: per entry it gathers the other
+// modes' rows, forms y prod_{n != k} A_n[i_n, :] and adds it to the LDS copy
+// of its rows; the block is flushed to G once.
+template <typename T, int D, int LANES, int VEC>
+__global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P, int splits)
+{
+    constexpr int S = 64 / LANES;
+    constexpr int U = (D == 0 || LANES < 4) ? 1 : (sizeof(T) == 4 ? 4 : 2);
+    constexpr int DM = D > 0 ? D : kMaxModes;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    T* part = reinterpret_cast<T*>(smem);
+    const int nwaves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / LANES, cl = lane % LANES;
+    const int col0 = cl * VEC;
+    const int R = P.R;
+    const bool col_ok = col0 < R;
+    const int dd = D > 0 ? D : P.sc.d;
+
+    const int b = blockIdx.x / splits;
+    const int split = blockIdx.x % splits;
+    // the bucketed mode owning bucket b: bucket_base is non-decreasing and
+    // modes that are not bucketed own an empty range
+    int k = 0;
+    for (int kk = 0; kk < dd; ++kk)
+        if (P.bucket_base[kk] <= b && b < P.bucket_base[kk + 1]) k = kk;
+    const int64_t r0 = (int64_t)(b - P.bucket_base[k]) << P.br_shift;
+    const int64_t rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[k] - r0);
+    for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) part[e] = T(0);
+    __syncthreads();
+
+    const int64_t j0 = P.nblocks * split / splits, j1 = P.nblocks * (split + 1) / splits;
+    for (int64_t j = j0 + wave; j < j1; j += nwaves) {
+        const int cnt = P.hist[(int64_t)b * P.nblocks + j];
+        const uint4* seg = P.entries + j * P.entry_cap + P.start[(int64_t)b * P.nblocks + j];
+        for (int base = 0; base < cnt; base += S * U) {
+            uint64_t key[U];
+            T y[U];
+            T a[U][DM][VEC];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * S + g;
+                const bool valid = e < cnt;
+                uint4 ent = valid ? seg[e] : make_uint4(0, 0, 0, 0);
+                key[u] = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
+                y[u] = valid ? entry_y<T>(ent) : T(0);
+#pragma unroll
+                for (int kk = 0; kk < DM; ++kk) {
+                    if (kk < dd) {
+                        if (kk != k && col_ok && valid) {
+                            const int64_t row = P.rowoff[kk] + (int64_t)unpack(P.sc.L, key[u], kk);
+                            load_cols<T, VEC>(P.A + row * R + col0, a[u][kk]);
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) a[u][kk][v] = T(1);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * S + g;
+                if (e >= cnt || !col_ok) continue;
+                const int64_t i = (int64_t)unpack(P.sc.L, key[u], k) - r0;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    T c = y[u];
+#pragma unroll
+                    for (int kk = 0; kk < DM; ++kk)
+                        if (kk < dd) c *= a[u][kk][v];
+                    atomicAdd(part + i * R + col0 + v, c);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    T* dst = P.G + (P.rowoff[k] + r0) * R;
+    for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) {
+        const T v = part[e];
+        if (v != T(0)) global_add(dst + e, v);
+    }
 }
 
 template <typename T>
@@ -235,16 +229,43 @@ __global__ void k_zero(T* __restrict__ p, int64_t n, double* __restrict__ loss_o
 
 template <typename T>
 using LGKernel = void (*)(const LGParams<T>);
+template <typename T>
+using BAKernel = void (*)(const LGParams<T>, int);
 
 // (lanes, vec) shapes built for each dtype
-#define GCP_LG_SHAPES_F32(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(4, 2) X(8, 2) X(16, 2)
-#define GCP_LG_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2)
+#define GCP_LG_SHAPES_F32(X) \
+    X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(64, 2) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4)
+#define GCP_LG_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(64, 2) X(64, 4)
+
+// The general-order (D = 0) float64 kernel with 64 lanes of one column is not
+// built: this toolchain fails to generate code for it on gfx950.  Even R uses
+// 32 lanes of two columns instead.
+template <typename T, int D, int LN, int VC>
+constexpr bool shape_built()
+{
+    return !(D == 0 && sizeof(T) == 8 && LN == 64 && VC == 1);
+}
 
 template <typename T, int D, int SRC>
 static LGKernel<T> pick_shape(int lanes, int vec)
 {
+#define GCP_CASE(LN, VC)                                          \
+    if constexpr (shape_built<T, D, LN, VC>())                    \
+        if (lanes == LN && vec == VC) return k_loss_grad<T, D, LN, VC, SRC>;
+    if constexpr (sizeof(T) == 4) {
+        GCP_LG_SHAPES_F32(GCP_CASE)
+    } else {
+        GCP_LG_SHAPES_F64(GCP_CASE)
+    }
+#undef GCP_CASE
+    return nullptr;
+}
+
+template <typename T, int D>
+static BAKernel<T> pick_bucket_shape(int lanes, int vec)
+{
 #define GCP_CASE(LN, VC) \
-    if (lanes == LN && vec == VC) return k_loss_grad<T, D, LN, VC, SRC>;
+    if (lanes == LN && vec == VC) return k_bucket_accum<T, D, LN, VC>;
     if constexpr (sizeof(T) == 4) {
         GCP_LG_SHAPES_F32(GCP_CASE)
     } else {
@@ -267,23 +288,33 @@ static LGKernel<T> pick_kernel(int d, int src, int lanes, int vec)
     return pick_shape<T, 0, 1>(lanes, vec);
 }
 
-// Default lane shape: the widest vector that divides R, then the fewest
-// lanes (power of two) that cover R.
+template <typename T>
+static BAKernel<T> pick_bucket_kernel(int d, int lanes, int vec)
+{
+    if (d == 3) return pick_bucket_shape<T, 3>(lanes, vec);
+    if (d == 4) return pick_bucket_shape<T, 4>(lanes, vec);
+    return pick_bucket_shape<T, 0>(lanes, vec);
+}
+
+// Default lane shape.  Global float atomics are executed past the L2 at a
+// fixed rate per request, and one request covers at most one 128-byte line,
+// so each gradient row is added by one instruction over consecutive lanes:
+// one column per lane while R <= 64, else the fewest columns per lane.
 template <typename T>
 static void default_shape(int R, int& lanes, int& vec)
 {
     const int vmax = sizeof(T) == 4 ? 4 : 2;
     vec = 1;
-    for (int v = vmax; v >= 2; v >>= 1)
-        if (R % v == 0 && R / v >= 2) { vec = v; break; }
+    while (vec < vmax && R > 64 * vec && R % (2 * vec) == 0) vec *= 2;
     const int need = (R + vec - 1) / vec;
     lanes = 8;
     while (lanes < need && lanes < 64) lanes <<= 1;
-    if (sizeof(T) == 4 && vec == 4 && need <= 4) lanes = need <= 2 ? 2 : 4;
-    if (vec == 2 && need <= 4) lanes = 4;
 }
 
-constexpr int kLdsPrivateBudget = 96 * 1024;   // bytes of private gradient per workgroup
+constexpr int kLdsPrivateBudget = 96 * 1024;    // bytes of private gradient per workgroup
+constexpr int kBucketLdsBudget = 32 * 1024;     // default bytes of one row block in LDS
+constexpr int kBucketMinSamples = 1 << 16;      // automatic bucketing only at or above this n
+constexpr int kMaxBuckets = 4096;
 
 template <typename T>
 static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
@@ -319,47 +350,90 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (R % vec != 0) return set_error(GCP_ERR_ARG, "vec = %d does not divide R = %d", vec, R);
     if (lanes * vec < R) return set_error(GCP_ERR_ARG, "lanes*vec = %d < R = %d", lanes * vec, R);
     const int src = smp ? 1 : 0;
+    if (sizeof(T) == 8 && t->d != 3 && t->d != 4 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
+        lanes = 32;
+        vec = 2;
+    }
     LGKernel<T> kern = pick_kernel<T>(t->d, src, lanes, vec);
     if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "tile lanes = %d, vec = %d not built for this dtype", lanes, vec);
     const uintptr_t align = (uintptr_t)vec * sizeof(T);
     if (((uintptr_t)A % align) != 0) return set_error(GCP_ERR_ARG, "A is not %d-byte aligned", (int)align);
+    const int d = t->d;
+    const int cus = device_cu_count(t->device);
 
-    // LDS privatisation of small modes
-    int block = 256;
-    int64_t nchunks = ceil_div(n, 64);
-    uint32_t mask = 0;
+    // scatter strategy per mode: LDS-private, bucketed or atomic
+    uint32_t lds_mask = 0, bucket_mask = 0;
     int64_t lds_elems = 0;
-    const int req_mask = tile ? tile->lds_modes : -1;
+    const int req_lds = tile ? tile->lds_modes : -1;
+    const int req_bucket = tile ? tile->bucket_modes : -1;
     if (!loss_only) {
-        for (int k = 0; k < t->d; ++k) {
+        for (int k = 0; k < d; ++k) {
             const int64_t elems = t->dims[k] * (int64_t)R;
             const bool fits = (lds_elems + elems) * (int64_t)sizeof(T) <= kLdsPrivateBudget;
             bool want;
-            if (req_mask >= 0) want = (req_mask >> k) & 1;
-            else want = fits && elems * 4 * (int64_t)device_cu_count(t->device) <= n * R;  // flush << scatter
+            // LDS float atomics (ds_add_f32) retire about one lane per three
+            // clocks on gfx950, far below the global atomic rate, so LDS
+            // privatisation is only used when asked for
+            if (req_lds >= 0) want = (req_lds >> k) & 1;
+            else want = false;
             if (want) {
                 if (!fits) return set_error(GCP_ERR_ARG, "LDS-private modes exceed %d bytes", kLdsPrivateBudget);
                 P.lds_off[k] = lds_elems;
                 lds_elems += elems;
-                mask |= 1u << k;
+                lds_mask |= 1u << k;
             }
         }
+        if (req_bucket > 0) bucket_mask = (uint32_t)req_bucket & ((1u << d) - 1) & ~lds_mask;
+        else if (req_bucket < 0 && t->ws && n >= kBucketMinSamples && n <= t->ws_max_samples) bucket_mask = ((1u << d) - 1) & ~lds_mask;
     }
-    if (mask) block = 1024;
+    // row-block geometry of the bucketed modes
+    int br_shift = 0, nb = 0, nbm = 0, spb = 0;
+    int64_t nblocks = 0;
+    if (bucket_mask) {
+        const int budget = (tile && tile->bucket_lds_bytes > 0) ? tile->bucket_lds_bytes : kBucketLdsBudget;
+        if (budget < 8192) return set_error(GCP_ERR_ARG, "bucket_lds_bytes = %d < 8192", budget);
+        while (((int64_t)2 << br_shift) * R * (int64_t)sizeof(T) <= budget && br_shift < 30) ++br_shift;
+        for (int k = 0; k < d; ++k) {
+            P.bucket_base[k] = nb;
+            if ((bucket_mask >> k) & 1u) {
+                nb += (int)ceil_div(t->dims[k], int64_t(1) << br_shift);
+                ++nbm;
+            }
+        }
+        for (int k = d; k <= kMaxModes; ++k) P.bucket_base[k] = nb;
+        spb = (tile && tile->bucket_block_samples > 0) ? tile->bucket_block_samples : 2048;
+        if (spb % 64 != 0 || spb < 512 || spb > 8192) return set_error(GCP_ERR_ARG, "bucket_block_samples = %d", spb);
+        nblocks = ceil_div(n, spb);
+        if (nb > kMaxBuckets) return set_error(GCP_ERR_UNSUPPORTED, "%d row blocks exceed %d", nb, kMaxBuckets);
+        if (!t->ws) return set_error(GCP_ERR_ARG, "bucketed scatter needs gcp_tensor_reserve first");
+        if (n > t->ws_max_samples || nblocks * spb * (int64_t)nbm > t->ws_entries || (int64_t)nb * nblocks > t->ws_hist)
+            return set_error(GCP_ERR_ARG, "workspace reserved by gcp_tensor_reserve is too small for this call");
+    }
+
+    int block = 256;
+    if (lds_mask) block = 1024;
     if (tile && tile->block > 0) {
         if (tile->block % 64 != 0 || tile->block > 1024) return set_error(GCP_ERR_ARG, "block = %d", tile->block);
         block = tile->block;
     }
     const int nwaves = block / 64;
     const int staging = nwaves * 64 * (8 + 2 * (int)sizeof(T));
-    const size_t lds_bytes = (size_t)staging + (size_t)lds_elems * sizeof(T);
+    size_t lds_bytes = (size_t)staging + (size_t)lds_elems * sizeof(T);
+    lds_bytes = (lds_bytes + 15) & ~(size_t)15;
+    const int bucket_lds = (int)lds_bytes;
+    if (bucket_mask) lds_bytes += (size_t)spb * (8 + sizeof(T)) + (size_t)nb * 8;
+    const int64_t nchunks = ceil_div(n, 64);
     int64_t grid;
-    {
+    st = prepare_lds(reinterpret_cast<const void*>(kern), lds_bytes, t->device);
+    if (st != GCP_OK) return st;
+    if (bucket_mask) {
+        grid = nblocks;
+    } else {
         int per_cu = 0;
         GCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), block,
                                                             lds_bytes));
         if (per_cu < 1) return set_error(GCP_ERR_UNSUPPORTED, "kernel does not fit on a CU (LDS %zu B)", lds_bytes);
-        const int64_t resident = (int64_t)per_cu * device_cu_count(t->device);
+        const int64_t resident = (int64_t)per_cu * cus;
         grid = std::max<int64_t>(1, std::min<int64_t>(resident, ceil_div(nchunks, nwaves)));
         if (tile && tile->grid > 0) grid = tile->grid;
     }
@@ -379,13 +453,26 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     P.semi = sp->kind == GCP_SAMPLE_SEMI_STRATIFIED;
     P.scale = (flags & GCP_SCALE_BY_DEV) ? (const T*)scale_dev : nullptr;
     P.loss_out = loss_out;
-    for (int k = 0; k < kMaxModes; ++k) P.rowoff[k] = k < t->d ? t->rowoff[k] : t->rowoff[t->d];
-    P.lds_mask = mask;
+    for (int k = 0; k < kMaxModes; ++k) P.rowoff[k] = k < d ? t->rowoff[k] : t->rowoff[d];
+    P.lds_mask = lds_mask;
     P.lds_elems = lds_elems;
     P.staging_bytes = staging;
+    P.bucket_mask = bucket_mask;
+    P.n_bucket_modes = nbm;
+    P.br_shift = br_shift;
+    P.nb = nb;
+    P.spb = spb;
+    P.nblocks = nblocks;
+    P.entry_cap = (int64_t)spb * nbm;
+    P.bucket_lds = bucket_lds;
+    if (bucket_mask) {
+        P.entries = (uint4*)t->ws;
+        P.hist = (int*)((char*)t->ws + t->ws_entries * 16);
+        P.start = P.hist + t->ws_hist;
+    }
 
     if (!accumulate) {
-        const int64_t gn = loss_only ? 0 : t->rowoff[t->d] * R;
+        const int64_t gn = loss_only ? 0 : t->rowoff[d] * R;
         if (gn > 0 || loss_out) {
             int64_t zb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(gn, 256), 4096));
             k_zero<T><<<(unsigned)zb, 256, 0, stream>>>((T*)G_out, gn, loss_out);
@@ -395,6 +482,20 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (n == 0) return GCP_OK;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds_bytes, stream, P);
     GCP_HIP(hipGetLastError());
+    if (bucket_mask) {
+        BAKernel<T> bk = pick_bucket_kernel<T>(d, lanes, vec);
+        if (!bk) return set_error(GCP_ERR_UNSUPPORTED, "no bucket kernel for lanes = %d, vec = %d", lanes, vec);
+        int splits = (tile && tile->bucket_splits > 0) ? tile->bucket_splits
+                                                        : (int)std::max<int64_t>(1, ceil_div(2 * (int64_t)cus, nb));
+        splits = (int)std::min<int64_t>(splits, nblocks);
+        const int bblock = (tile && tile->bucket_block > 0) ? tile->bucket_block : 512;
+        if (bblock % 64 != 0 || bblock > 1024) return set_error(GCP_ERR_ARG, "bucket_block = %d", bblock);
+        const size_t part_bytes = ((size_t)1 << br_shift) * R * sizeof(T);
+        st = prepare_lds(reinterpret_cast<const void*>(bk), part_bytes, t->device);
+        if (st != GCP_OK) return st;
+        hipLaunchKernelGGL(bk, dim3((unsigned)(nb * splits)), dim3(bblock), part_bytes, stream, P, splits);
+        GCP_HIP(hipGetLastError());
+    }
     return GCP_OK;
 }
 

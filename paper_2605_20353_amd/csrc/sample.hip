@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleCtx<T> c, int64_t n, int64
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
         uint64_t key;
         T x, w;
-        draw_sample<T, D>(c, s, key, x, w);
+        draw_sample<T, D>(c, c.step, s, key, x, w);
 #pragma unroll
         for (int k = 0; k < kMaxModes; ++k)
             if (k < dd) coords[s * dd + k] = (int64_t)unpack(c.L, key, k);

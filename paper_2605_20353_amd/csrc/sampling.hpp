@@ -43,12 +43,14 @@ struct SampleCtx {
     uint32_t* status;
 };
 
-// Fills the packed key, value and weight of sample s in [0, p + q).
+// Fills the packed key, value and weight of sample s in [0, p + q) of
+// iteration `step` (the second Philox counter word).
 template <typename T, int D>
-__device__ __forceinline__ void draw_sample(const SampleCtx<T>& c, int64_t s, uint64_t& key, T& x, T& w)
+__device__ __forceinline__ void draw_sample(const SampleCtx<T>& c, uint64_t step, int64_t s, uint64_t& key, T& x,
+                                            T& w)
 {
     if (c.kind == GCP_SAMPLE_UNIFORM) {
-        key = draw_cell_key<D>(c.L, c.d, c.seed, c.client, (uint64_t)s, c.step, kStreamUniform, 0);
+        key = draw_cell_key<D>(c.L, c.d, c.seed, c.client, (uint64_t)s, step, kStreamUniform, 0);
         int64_t lin = 0;
         const int dd = D > 0 ? D : c.d;
 #pragma unroll
@@ -59,7 +61,7 @@ __device__ __forceinline__ void draw_sample(const SampleCtx<T>& c, int64_t s, ui
         return;
     }
     if (s < c.p) {
-        U64x4 o = philox4x64_10((uint64_t)s, c.step, kStreamNonzero, 0, c.seed, c.client);
+        U64x4 o = philox4x64_10((uint64_t)s, step, kStreamNonzero, 0, c.seed, c.client);
         int64_t j = (int64_t)range_map(o.v[0], (uint64_t)c.N);
         // one 16-byte streaming load: records are touched once per draw
         u32x4 raw = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(c.rec + j));
@@ -71,7 +73,7 @@ __device__ __forceinline__ void draw_sample(const SampleCtx<T>& c, int64_t s, ui
     const uint64_t z = (uint64_t)(s - c.p);
     const bool search = c.kind == GCP_SAMPLE_STRATIFIED;
     for (int a = 0;; ++a) {
-        key = draw_cell_key<D>(c.L, c.d, c.seed, c.client, z, c.step, kStreamZero, (uint64_t)a);
+        key = draw_cell_key<D>(c.L, c.d, c.seed, c.client, z, step, kStreamZero, (uint64_t)a);
         if (!search || !table_contains(c.table, c.table_mask, c.table_log2, key)) break;
         if (a + 1 >= c.max_attempts) {
             atomicOr(c.status, kStatusSampling);

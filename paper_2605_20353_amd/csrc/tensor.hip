@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -45,6 +46,27 @@ int device_cu_count(int device)
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+gcp_status prepare_lds(const void* fn, size_t bytes, int device)
+{
+    static int cached[64] = {};
+    int maxb = 65536;
+    if (device >= 0 && device < 64) {
+        if (!cached[device]) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, device) != hipSuccess || v <= 0)
+                if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || v <= 0)
+                    v = 65536;
+            cached[device] = v;
+        }
+        maxb = cached[device];
+    }
+    if (bytes > (size_t)maxb)
+        return set_error(GCP_ERR_UNSUPPORTED, "kernel needs %zu bytes of LDS, the device allows %d", bytes, maxb);
+    if (bytes > 65536)
+        GCP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return GCP_OK;
+}
 
 static int bits_for(int64_t n)
 {
@@ -147,6 +169,7 @@ static void free_tensor(gcp_tensor_s* t)
     if (t->rec) (void)hipFree(t->rec);
     if (t->table) (void)hipFree(t->table);
     if (t->status) (void)hipFree(t->status);
+    if (t->ws) (void)hipFree(t->ws);
     (void)hipSetDevice(cur);
     delete t;
 }
@@ -245,7 +268,49 @@ gcp_status gcp_tensor_destroy(gcp_tensor t)
     return GCP_OK;
 }
 
-int64_t gcp_tensor_device_bytes(gcp_tensor t) { return t ? t->owned_bytes : 0; }
+int64_t gcp_tensor_device_bytes(gcp_tensor t) { return t ? t->owned_bytes + t->ws_bytes : 0; }
+
+gcp_status gcp_tensor_reserve(gcp_tensor t, int64_t max_samples, int R, hipStream_t stream)
+{
+    clear_error();
+    if (!t) return set_error(GCP_ERR_ARG, "tensor is NULL");
+    if (max_samples < 0 || max_samples > (int64_t(1) << 40)) return set_error(GCP_ERR_ARG, "max_samples");
+    if (R < 1 || R > 256) return set_error(GCP_ERR_ARG, "R = %d outside [1, 256]", R);
+    (void)stream;
+    int cur = 0;
+    GCP_HIP(hipGetDevice(&cur));
+    GCP_HIP(hipSetDevice(t->device));
+    GCP_HIP(hipDeviceSynchronize());
+    if (t->ws) {
+        GCP_HIP(hipFree(t->ws));
+        t->ws = nullptr;
+        t->ws_entries = t->ws_hist = t->ws_bytes = t->ws_max_samples = 0;
+    }
+    if (max_samples == 0) { GCP_HIP(hipSetDevice(cur)); return GCP_OK; }
+    // smallest row block: 8 KiB of LDS; fewest samples per workgroup: 512
+    const int64_t esize = t->dt == GCP_F32 ? 4 : 8;
+    int br_shift = 0;
+    while (((int64_t)2 << br_shift) * R * esize <= 8192 && br_shift < 30) ++br_shift;
+    int64_t nb = 0;
+    for (int k = 0; k < t->d; ++k) nb += ceil_div(t->dims[k], int64_t(1) << br_shift);
+    nb = std::min<int64_t>(nb, 4096);
+    const int64_t nblocks = ceil_div(max_samples, 512);
+    const int64_t entries = (max_samples + 8192) * t->d;
+    const int64_t hist = nb * nblocks;
+    const int64_t bytes = entries * 16 + hist * 8;
+    hipError_t e = hipMalloc(&t->ws, (size_t)bytes);
+    if (e != hipSuccess) {
+        t->ws = nullptr;
+        (void)hipSetDevice(cur);
+        return hip_error(e, "hipMalloc(workspace)");
+    }
+    t->ws_entries = entries;
+    t->ws_hist = hist;
+    t->ws_bytes = bytes;
+    t->ws_max_samples = max_samples;
+    GCP_HIP(hipSetDevice(cur));
+    return GCP_OK;
+}
 
 gcp_status gcp_device_status(gcp_tensor t, hipStream_t stream)
 {

@@ -44,3 +44,16 @@ def test_host_argument_errors_without_gpu():
     assert b"NULL" in L.gcp_last_error()
     # n = 0 is a no-op success
     assert L.gcp_adam_step(None, None, None, None, 0, 0, 1, 1e-3, .9, .999, 1e-8, 0.0, 0, None) == _lib.GCP_OK
+
+
+def test_struct_layouts_match_the_binding():
+    import ctypes as C
+    from paper_2605_20353_amd import fedadam
+    L = _lib.lib()
+    L.gcp_struct_size.restype = C.c_int64
+    L.gcp_struct_size.argtypes = [C.c_char_p]
+    for name, cls in [("gcp_sample_params", _lib.gcp_sample_params), ("gcp_samples", _lib.gcp_samples),
+                      ("gcp_tile", _lib.gcp_tile), ("gcp_fed_client", fedadam.gcp_fed_client),
+                      ("gcp_fed_desc", fedadam.gcp_fed_desc)]:
+        assert L.gcp_struct_size(name.encode()) == C.sizeof(cls), name
+    assert L.gcp_struct_size(b"nope") == -1

@@ -1,0 +1,126 @@
+"""Differentiation: the sampled GCP objective as a torch.autograd.Function
+whose backward is the sampled MTTKRP (recomputed samples, or stored ones),
+checked with torch.autograd.gradcheck, central finite differences and the
+FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_20353_amd import _lib as G
+from paper_2605_20353_amd import synth
+from paper_2605_20353_amd.autograd import GCPLoss, KruskalModel, gcp_loss
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _dense_case(dims, Rtrue, seed, dtype, gpu):
+    X, _ = synth.dense_gaussian(dims, Rtrue, seed=seed, dtype=torch.float64, device=gpu)
+    return X, G.DenseTensor(dims, X.to(dtype))
+
+
+@pytest.mark.parametrize("recompute", [True, False])
+def test_gradcheck_dense_gaussian(gpu, recompute):
+    dims, R = [5, 4, 3, 6], 3
+    _, t = _dense_case(dims, 2, 1, torch.float64, gpu)
+    A = synth.init_model(dims, R, 3, dist="normal", dtype=torch.float64, device=gpu).requires_grad_(True)
+    sp = G.SampleParams("uniform", 300, 0, seed=4, step=1)
+    f = lambda a: gcp_loss(a, t, R, "gaussian", sp, recompute=recompute)
+    # float atomics make repeated backward passes differ in the last bits
+    assert torch.autograd.gradcheck(f, (A,), eps=1e-6, atol=1e-7, rtol=1e-6, nondet_tol=1e-9)
+
+
+@pytest.mark.parametrize("loss", ["poisson", "bernoulli_logit"])
+@pytest.mark.parametrize("recompute", [True, False])
+def test_gradcheck_sparse_stratified(gpu, loss, recompute):
+    dims, R = [7, 6, 5], 2
+    data = synth.count_tensor(dims, 2, 40, seed=5, binary=(loss == "bernoulli_logit"))
+    t = G.SparseTensor(dims, data.coords.to(gpu), data.vals.to(gpu))
+    A = (0.3 + synth.init_model(dims, R, 6, dtype=torch.float64, device=gpu)).requires_grad_(True)
+    sp = G.SampleParams("stratified", 30, 40, seed=7, step=2)
+    f = lambda a: gcp_loss(a, t, R, loss, sp, recompute=recompute)
+    assert torch.autograd.gradcheck(f, (A,), eps=1e-6, atol=1e-6, rtol=1e-5, nondet_tol=1e-9)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_backward_equals_oracle_gradient(gpu, dtype):
+    dims, R = [30, 20, 16, 8], 16
+    data = synth.count_tensor(dims, 4, 800, seed=8)
+    t = G.SparseTensor(dims, data.coords.to(gpu), data.vals.to(dtype).to(gpu))
+    model = KruskalModel(dims, R, init=0.2 + synth.init_model(dims, R, 9, dtype=dtype), dtype=dtype, device=gpu)
+    sp = G.SampleParams("stratified", 5000, 4000, seed=10, step=3)
+    for recompute in (True, False):
+        model.zero_grad()
+        F = model(t, "poisson", sp, recompute=recompute)
+        (2.0 * F).backward()
+        to = oracle.SparseTensor(dims, data.coords.numpy(), data.vals.to(dtype).double().numpy())
+        sc, sx, sw = oracle.sample_stratified(to, 5000, 4000, 10, 3)
+        Go, Fo = oracle.loss_grad(dims, R, model.A.detach().double().cpu().numpy(), sc, sx, sw, "poisson")
+        g = model.A.grad.double().cpu().numpy().reshape(-1)
+        tol = 1e-12 if dtype == torch.float64 else 1e-5
+        assert np.linalg.norm(g - 2 * Go) <= tol * np.linalg.norm(2 * Go)
+        assert abs(F.item() - Fo) <= tol * abs(Fo)
+        assert F.dtype == torch.float64
+
+
+def test_config3_shape_fd_rank16_fp64(gpu):
+    """Dense Gaussian 200 x 200 x 200 x 50 (rank-16 model + N(0, 0.1^2)
+    noise), rank 16, 2^22 uniform samples, FP64: the hand-written backward
+    equals central finite differences of the forward on sampled entries."""
+    dims, R = [200, 200, 200, 50], 16
+    say("config-3 fp64: generating the dense tensor")
+    _, t = _dense_case(dims, 16, 2608, torch.float64, gpu)
+    A = (synth.init_model(dims, R, 2708, dist="normal", dtype=torch.float64, device=gpu)
+         * synth.normal_init_scale(R, 4)).requires_grad_(True)
+    sp = G.SampleParams("uniform", 1 << 22, 0, seed=20353, step=0)
+    F = gcp_loss(A, t, R, "gaussian", sp)
+    F.backward()
+    g = A.grad.detach().reshape(-1)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(A.numel(), 24, replace=False)
+    Ad = A.detach().reshape(-1)
+    for i in idx:
+        a0 = Ad[i].item()
+        # F~ is quadratic in any single entry under the Gaussian loss, so the
+        # central difference has no truncation error and h can be large
+        h = 1e-2 * max(1.0, abs(a0))
+        Ap = Ad.clone(); Ap[i] = a0 + h
+        Am = Ad.clone(); Am[i] = a0 - h
+        with torch.no_grad():
+            fp = GCPLoss.apply(Ap, t, R, "gaussian", sp, True, None).item()
+            fm = GCPLoss.apply(Am, t, R, "gaussian", sp, True, None).item()
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[i].item()) <= 1e-6 * max(abs(fd), 1e-3 * g.abs().max().item()), (i, fd, g[i].item())
+
+
+def test_config3_fp32_backward_vs_fp64_oracle(gpu):
+    """The FP32 backward of the config-3 workload against the FP64 oracle on
+    the oracle's own uniform samples: <= 1e-5 relative per mode."""
+    dims, R = [200, 200, 200, 50], 16
+    say("config-3 fp32: generating the dense tensor")
+    X, t = _dense_case(dims, 16, 2608, torch.float32, gpu)
+    A = (synth.init_model(dims, R, 2708, dist="normal", dtype=torch.float32, device=gpu)
+         * synth.normal_init_scale(R, 4)).requires_grad_(True)
+    s = 1 << 22
+    sp = G.SampleParams("uniform", s, 0, seed=20353, step=0)
+    F = gcp_loss(A, t, R, "gaussian", sp)
+    F.backward()
+    say("config-3 fp32: oracle")
+    Xh = X.to(torch.float32).double().cpu().numpy()
+    oc, ox, ow = oracle.sample_uniform(dims, Xh, s, 20353, 0)
+    Go, Fo = oracle.loss_grad(dims, R, A.detach().double().cpu().numpy(), oc, ox, ow, "gaussian")
+    g = A.grad.double().cpu().numpy().reshape(-1, R)
+    Go = Go.reshape(-1, R)
+    off = 0
+    for n in dims:
+        err = np.linalg.norm(g[off:off + n] - Go[off:off + n]) / np.linalg.norm(Go[off:off + n])
+        assert err <= 1e-5, err
+        off += n
+    assert abs(F.item() - Fo) <= 1e-5 * abs(Fo)

@@ -1,0 +1,168 @@
+"""GCP-FedAdam rounds on the GPU (batched persistent launch, with and without
+HIP-graph replay, and per-client launches) against the oracle's FedAdam round
+(Alg. gcp-fed-iter) and against each other."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_20353_amd import _lib as G
+from paper_2605_20353_amd import synth
+from paper_2605_20353_amd.autotune import tune_fedadam
+from paper_2605_20353_amd.fedadam import FedAdam, FedConfig, FedTile
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _blocks(gdims, grid, R, nmin, nmax, seed):
+    return synth.fed_blocks(gdims, grid, R, nmin, nmax, seed=seed)
+
+
+def _gpu_clients(blocks, dtype, gpu):
+    out = []
+    for bl in blocks:
+        t = G.SparseTensor(bl.data.dims, bl.data.coords.to(gpu), bl.data.vals.to(dtype).to(gpu))
+        out.append((t, bl.row_base))
+    return out
+
+
+def _oracle_clients(blocks, R, dtype):
+    out = []
+    for bl in blocks:
+        t = oracle.SparseTensor(bl.data.dims, bl.data.coords.numpy(), bl.data.vals.to(dtype).double().numpy())
+        n = sum(bl.data.dims) * R
+        out.append(oracle.FedClient(t, np.array(bl.row_base), np.zeros(n), np.zeros(n), np.zeros(n)))
+    return out
+
+
+def _run_oracle(blocks, gdims, R, U0, cfg, rounds, dtype):
+    ocl = _oracle_clients(blocks, R, dtype)
+    U = U0.double().cpu().numpy().reshape(-1).copy()
+    Bs, Cs = np.zeros_like(U), np.zeros_like(U)
+    ap_c = oracle.AdamParams(cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.lower)
+    ap_s = oracle.AdamParams(cfg.meta_lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.lower)
+    st = 0
+    for r in range(rounds):
+        st = oracle.fedadam_round(ocl, gdims, R, U, Bs, Cs, st, r, cfg.tau, cfg.loss, cfg.p, cfg.q, cfg.seed,
+                                  ap_c, ap_s)
+    return U, ocl
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+SMALL = dict(gdims=[40, 36, 20], grid=(2, 2, 2), R=3, nmin=30, nmax=150)
+
+
+@pytest.mark.parametrize("mode", ["batched_graph", "batched", "plain"])
+def test_fp64_rounds_match_oracle(gpu, mode):
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2609)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2709, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=3, loss="poisson", p=64, q=64, seed=20353, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg,
+                  batched=mode != "plain", use_graph=mode == "batched_graph")
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0, cfg, 2, torch.float64)
+    assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10
+    for cl, oc in zip(fed.clients, ocl):
+        assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
+        assert _rel(cl.B.cpu().numpy(), oc.B) <= 1e-10
+        assert torch.count_nonzero(cl.G).item() == 0
+
+
+def test_fp64_workgroups_per_client_sweep(gpu):
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], 400, seed=2610)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2710, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=300, q=200, seed=5, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    Uo, _ = _run_oracle(blocks, gdims, R, U0, cfg, 1, torch.float64)
+    for tile in (FedTile(1, 64), FedTile(3, 128), FedTile(16, 256), FedTile(2, 1024)):
+        fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, tile=tile)
+        fed.round(0)
+        fed.status()
+        assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10, tile
+        fed.close()
+
+
+@pytest.mark.parametrize("shape", [(32, 1), (16, 2), (8, 4)])
+def test_fp32_batched_equals_plain_and_oracle(gpu, shape):
+    gdims, grid, R = [200, 160, 60], (4, 2, 2), 32
+    blocks = _blocks(gdims, grid, R, 200, 2000, seed=2611)
+    U0 = 0.1 + 0.9 * synth.init_model(gdims, R, 2711, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=4, loss="poisson", p=1024, q=1024, seed=11, lr=1e-3, meta_lr=1e-3, lower=0.0)
+    tile = FedTile(lanes=shape[0], vec=shape[1])
+    feds = {}
+    for mode in ("batched_graph", "plain"):
+        fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg,
+                      batched=mode != "plain", use_graph=mode == "batched_graph", tile=tile)
+        for r in range(2):
+            fed.round(r)
+        fed.status()
+        feds[mode] = fed
+    Ub = feds["batched_graph"].U.double().cpu().numpy()
+    Up = feds["plain"].U.double().cpu().numpy()
+    assert _rel(Ub, Up) <= 1e-5
+    Uo, _ = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    assert _rel(Ub, Uo) <= 1e-5
+
+
+def test_graph_replays_stay_exact(gpu):
+    """Several graph replays with eager work and synchronisations in between
+    each equal the eager (non-graph) batched rounds."""
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2612)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2712, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=64, q=64, seed=9, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    fg = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=True)
+    fe = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=False)
+    for r in range(4):
+        fg.round(r)
+        fe.round(r)
+        junk = torch.randn(1000, device=gpu).sum().item()     # eager work between replays
+        torch.cuda.synchronize()
+        assert junk == junk
+        assert _rel(fg.U.cpu().numpy(), fe.U.cpu().numpy()) <= 1e-12, r
+
+
+def test_autotuner_keeps_state_and_picks_a_shape(gpu, tmp_path, monkeypatch):
+    monkeypatch.setenv("GCP_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2613)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2713, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=64, q=64, seed=3, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg)
+    before = fed.U.clone()
+    tile = tune_fedadam(fed, candidates=[FedTile(1, 256), FedTile(4, 256), FedTile(2, 512)])
+    assert torch.equal(fed.U, before)
+    assert (tmp_path / "tune.json").exists()
+    fed.round(0)
+    fed.status()
+    Uo, _ = _run_oracle(blocks, gdims, R, U0, cfg, 1, torch.float64)
+    assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10
+    assert isinstance(tile, FedTile)
+
+
+def test_create_errors(gpu):
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2614)
+    U0 = synth.init_model(gdims, R, 1, dtype=torch.float64).to(gpu)
+    cfg = FedConfig(R=R, tau=1, p=8, q=8)
+    cl = _gpu_clients(blocks, torch.float64, gpu)
+    bad = [(t, [b[0] + 30, b[1], b[2]]) for t, b in cl]          # blocks outside the global dims
+    with pytest.raises(G.GCPError) as e:
+        FedAdam(bad, gdims, U0, cfg)
+    assert e.value.code == G.GCP_ERR_ARG
+    with pytest.raises(G.GCPError) as e:                         # more workgroups than the GPU holds
+        FedAdam(cl, gdims, U0, cfg, tile=FedTile(workgroups_per_client=100000))
+    assert e.value.code == G.GCP_ERR_UNSUPPORTED

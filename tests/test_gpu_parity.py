@@ -178,6 +178,63 @@ def test_every_tile_matches_oracle(gpu, dtype, name):
     assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
 
 
+BUCKET_TILES = [
+    dict(),                                                          # automatic
+    dict(bucket_modes=7, lds_modes=0, bucket_lds_bytes=8192, bucket_block_samples=512, bucket_splits=3),
+    dict(bucket_modes=5, lds_modes=0, bucket_block_samples=1024, bucket_splits=1, bucket_block=64),
+    dict(bucket_modes=7, lds_modes=2, bucket_block_samples=4096, bucket_block=1024),
+    dict(bucket_modes=7, lds_modes=0, bucket_block_samples=8192, bucket_lds_bytes=65536),
+]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("loss", ["poisson", "gaussian"])
+@pytest.mark.parametrize("pq", [(70000, 50001), (3000, 2000)])
+def test_bucketed_scatter_matches_oracle(gpu, dtype, loss, pq):
+    """Row-bucketed (sort-by-row) scatter, alone and mixed with the LDS and
+    atomic strategies, ragged sample counts, against the oracle."""
+    t_gpu, t_ora, dims, R = make_case("r32", dtype, gpu)
+    t_gpu.reserve(sum(pq), R)
+    A = model(dims, R, dtype, gpu, dist="normal" if loss == "gaussian" else "uniform")
+    sp = G.SampleParams("stratified", pq[0], pq[1], seed=31, step=2)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, loss, sp)
+    for tl in BUCKET_TILES:
+        say(f"bucketed {dtype} {loss} {pq} {tl}")
+        Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, loss, tile=G.Tile(**tl))
+        t_gpu.status()
+        assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype], tl
+        assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+    # a scale and accumulation go through the bucketed path too
+    scale = torch.tensor([0.5], dtype=dtype, device=gpu)
+    Gs, _ = G.gcp_loss_grad(t_gpu, sp, A, R, loss, scale=scale, tile=G.Tile(bucket_modes=7, lds_modes=0))
+    Gs, _ = G.gcp_loss_grad(t_gpu, sp, A, R, loss, G=Gs, accumulate=True, scale=scale,
+                            tile=G.Tile(bucket_modes=7, lds_modes=0))
+    assert split_rel_err(Gs.double().cpu().numpy(), Go, dims, R) <= 4 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_bucketed_scatter_4way_r64(gpu, dtype):
+    t_gpu, t_ora, dims, R = make_case("r64_4way", dtype, gpu)
+    t_gpu.reserve(40000, R)
+    A = model(dims, R, dtype, gpu)
+    sp = G.SampleParams("stratified", 20000, 19999, seed=5, step=9)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    for tl in (dict(bucket_modes=15, lds_modes=0), dict(bucket_modes=15, lds_modes=0, bucket_lds_bytes=8192)):
+        Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(**tl))
+        assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype], tl
+
+
+def test_bucketed_scatter_needs_workspace(gpu):
+    t_gpu, _, dims, R = make_case("r32", torch.float32, gpu)
+    A = model(dims, R, torch.float32, gpu)
+    sp = G.SampleParams("stratified", 1000, 1000, seed=1)
+    with pytest.raises(G.GCPError):
+        G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(bucket_modes=1))
+    t_gpu.reserve(1000, R)
+    with pytest.raises(G.GCPError):     # reserved for fewer samples than requested
+        G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(bucket_modes=1))
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_materialised_equals_fused(gpu, dtype):
     t_gpu, t_ora, dims, R = make_case("4way", dtype, gpu)
