@@ -35,7 +35,9 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 from paper_2605_20353_amd import _lib as G  # noqa: E402
-from paper_2605_20353_amd import synth  # noqa: E402
+from paper_2605_20353_amd import autotune, synth  # noqa: E402
+from paper_2605_20353_amd.autograd import gcp_loss  # noqa: E402
+from paper_2605_20353_amd.fedadam import FedAdam, FedConfig  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 DIMS = [10000, 8000, 6000]
@@ -86,14 +88,14 @@ def build_workload(dev):
     data = synth.count_tensor(DIMS, RANK, NNZ, seed=DATA_SEED, dist="gamma", device=dev)
     log(f"  generated in {time.time() - t0:.1f} s")
     t = G.SparseTensor(DIMS, data.coords, data.vals.to(torch.float32))
+    t.reserve(P + Q, RANK)
     torch.cuda.synchronize()
-    log(f"  tensor handle: {t.device_bytes() / 2**30:.2f} GiB of records + membership table")
+    log(f"  tensor handle: {t.device_bytes() / 2**30:.2f} GiB of records, membership table and workspace")
     A = synth.init_model(DIMS, RANK, DATA_SEED + 100, dist="uniform", device=dev, dtype=torch.float32)
     return data, t, A
 
 
-def run_gpu(t, A, steps: int, warmup: int):
-    dev = A.device
+def run_gpu(t, A, steps: int, warmup: int, tile):
     Gr = torch.zeros_like(A)
     B = torch.zeros_like(A)
     Cm = torch.zeros_like(A)
@@ -101,7 +103,7 @@ def run_gpu(t, A, steps: int, warmup: int):
 
     def step(k):
         sp = G.SampleParams("stratified", P, Q, seed=SAMPLE_SEED, step=k)
-        G.gcp_loss_grad(t, sp, A, RANK, "poisson", G=Gr, accumulate=True, want_loss=False)
+        G.gcp_loss_grad(t, sp, A, RANK, "poisson", G=Gr, accumulate=True, want_loss=False, tile=tile)
         return sp
 
     for k in range(warmup):
@@ -126,6 +128,84 @@ def run_gpu(t, A, steps: int, warmup: int):
     _, L = G.gcp_loss_grad(t, sp, A, RANK, "poisson", loss_only=True)
     torch.cuda.synchronize()
     return (t1 - t0), kms, float(L.item()), n_params
+
+
+def _time_ms(fn, reps: int, warmup: int) -> float:
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def run_fedadam(dev, rounds: int):
+    """GCP-FedAdam, 64 clients on a 4x4x4 block grid over 20000x20000x2000,
+    1e5..5e6 nonzeros per client (log-uniform), rank 32 FP32, tau = 10 local
+    steps of 2^16 + 2^16 samples, then the server step: ms per round for
+    per-client launches and for the batched persistent launch (graph replay,
+    autotuned launch shape)."""
+    gd, grid, R = [20000, 20000, 2000], (4, 4, 4), 32
+    log("fedadam: generating 64 client blocks")
+    blocks = synth.fed_blocks(gd, grid, R, 1e5, 5e6, seed=2610, device=dev)
+    nnz = sum(b.data.nnz for b in blocks)
+    clients = [(G.SparseTensor(b.data.dims, b.data.coords, b.data.vals.to(torch.float32)), b.row_base)
+               for b in blocks]
+    del blocks
+    U0 = synth.init_model(gd, R, 2710, device=dev, dtype=torch.float32)
+    cfg = FedConfig(R=R, tau=10, loss="poisson", p=1 << 16, q=1 << 16, seed=SAMPLE_SEED, lr=1e-3, meta_lr=1e-3,
+                    lower=0.0)
+    out = {"workload": "GCP-FedAdam, 64 clients (4x4x4 grid over 20000x20000x2000), "
+                       f"{nnz} nonzeros, rank 32 FP32, tau 10 x (2^16 + 2^16) samples per client",
+           "nnz": nnz}
+    plain = FedAdam(clients, gd, U0, cfg, batched=False)
+    out["plain_ms_per_round"] = _time_ms(lambda: plain.round(0), rounds, 1)
+    plain.status()
+    plain.close()
+    fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True)
+    tile = autotune.tune_fedadam(fed, rounds=1, warmup=1, use_cache=False)
+    out["batched_tile"] = {"workgroups_per_client": tile.workgroups_per_client, "block": tile.block,
+                           "lanes": tile.lanes, "vec": tile.vec}
+    out["batched_ms_per_round"] = _time_ms(lambda: fed.round(0), rounds, 1)
+    fed.status()
+    fed.close()
+    out["speedup"] = out["plain_ms_per_round"] / out["batched_ms_per_round"]
+    out["samples_per_round"] = 64 * 10 * (cfg.p + cfg.q)
+    out["batched_samples_per_s"] = out["samples_per_round"] / (out["batched_ms_per_round"] * 1e-3)
+    log(f"fedadam: plain {out['plain_ms_per_round']:.2f} ms, batched {out['batched_ms_per_round']:.2f} ms per "
+        f"round -> {out['speedup']:.2f}x")
+    return out
+
+
+def run_autograd(dev, which: str, reps: int):
+    """Forward + backward of the sampled objective as a torch.autograd
+    Function (backward recomputes the samples and model values)."""
+    if which == "dense_gaussian":
+        dims, R, loss, s = [200, 200, 200, 50], 16, "gaussian", 1 << 22
+        X, _ = synth.dense_gaussian(dims, 16, seed=2608, device=dev, dtype=torch.float32)
+        t = G.DenseTensor(dims, X)
+        sp = G.SampleParams("uniform", s, 0, seed=SAMPLE_SEED, step=0)
+        desc = "dense Gaussian 200x200x200x50 FP32, rank 16, 2^22 uniform samples"
+    else:
+        dims, R, loss, s = [5000, 5000, 500, 100], 64, "bernoulli_logit", 1 << 23
+        data = synth.count_tensor(dims, 64, 100_000_000, seed=2609, device=dev, binary=True)
+        t = G.SparseTensor(dims, data.coords, data.vals.to(torch.float32))
+        t.reserve(s, R)
+        del data
+        sp = G.SampleParams("stratified", s // 2, s // 2, seed=SAMPLE_SEED, step=0)
+        desc = "binary 5000x5000x500x100 with 1e8 ones, Bernoulli-logit, rank 64 FP32, 2^22 + 2^22 samples"
+    A = (synth.init_model(dims, R, 2708, dist="normal", device=dev, dtype=torch.float32)
+         * synth.normal_init_scale(R, len(dims))).requires_grad_(True)
+
+    def fb():
+        A.grad = None
+        gcp_loss(A, t, R, loss, sp).backward()
+
+    ms = _time_ms(fb, reps, 2)
+    log(f"autograd {which}: {ms:.3f} ms per forward+backward")
+    return {"workload": desc, "ms_per_forward_backward": ms, "samples_per_s": s / (ms * 1e-3)}
 
 
 def run_cpu_baseline(data, A_init: np.ndarray, steps: int):
@@ -156,6 +236,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the GCP-FedAdam round and autograd measurements")
+    ap.add_argument("--fed-rounds", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times, so that "
                          "rocprofv3's FETCH_SIZE / WRITE_SIZE can be calibrated against known bytes")
@@ -176,8 +259,11 @@ def main():
     dev = torch.device("cuda:0")
     data, t, A = build_workload(dev)
     A0 = A.cpu().numpy().copy()
+    sp0 = G.SampleParams("stratified", P, Q, seed=SAMPLE_SEED, step=0)
+    tile = autotune.tune_loss_grad(t, sp0, A, RANK, "poisson", reps=10)
+    log(f"autotuned sampled-gradient tile: {tile}")
     log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
-    wall, kms, loss_est, n_params = run_gpu(t, A, args.steps, args.warmup)
+    wall, kms, loss_est, n_params = run_gpu(t, A, args.steps, args.warmup, tile)
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps * (P + Q) / wall
     kmean = float(np.mean(kms))
@@ -191,10 +277,22 @@ def main():
             "algorithmic_bytes_per_launch": alg}
     log(f"step {ms_per_step:.4f} ms, {value:.4g} samples/s; loss_grad kernel {kmean:.4f} ms "
         f"-> {achieved:.0f} GB/s algorithmic")
+    roof["tile"] = {"lanes": tile.lanes, "vec": tile.vec, "block": tile.block, "lds_modes": tile.lds_modes,
+                    "bucket_modes": tile.bucket_modes, "bucket_block_samples": tile.bucket_block_samples,
+                    "bucket_splits": tile.bucket_splits}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(data, A0, args.cpu_steps)
         log(f"cpu baseline {cpu['value']:.4g} samples/s")
+    del data, t
+    torch.cuda.empty_cache()
+    extras = {}
+    if not args.no_extras:
+        extras["fedadam"] = run_fedadam(dev, args.fed_rounds)
+        torch.cuda.empty_cache()
+        extras["autograd_dense_gaussian"] = run_autograd(dev, "dense_gaussian", 10)
+        torch.cuda.empty_cache()
+        extras["autograd_binary_bernoulli"] = run_autograd(dev, "binary_bernoulli", 5)
     out = {
         "metric": "sampled gradient entries/sec + HBM GB/s fraction; batched vs plain speedup",
         "value": value,
@@ -216,6 +314,8 @@ def main():
         "params": n_params,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched_vs_plain_speedup": extras.get("fedadam", {}).get("speedup"),
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -86,9 +86,14 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int c = blockIdx.x / F.W, w = blockIdx.x % F.W;
     const FedClientDev<T>& C = F.clients[c];
-    const LGParams<T>& P = C.P;
+    // a private copy: read once, then held in registers -- read through the
+    // global reference, every field would be reloaded after each atomic
+    const LGParams<T> P = C.P;
     T* M = const_cast<T*>(P.A);
     T* G = P.G;
+    T* const Bc = C.B;
+    T* const Cc = C.C;
+    const int64_t nparams = C.nparams;
     const int nwaves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint64_t* skey = reinterpret_cast<uint64_t*>(smem) + wave * 64;
@@ -113,12 +118,12 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
         fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
         const int64_t t = round * F.tau + j + 1;
         const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
-        for (int64_t e = tid; e < C.nparams; e += nthreads) {
-            T p = M[e], b = C.B[e], cc = C.C[e];
+        for (int64_t e = tid; e < nparams; e += nthreads) {
+            T p = M[e], b = Bc[e], cc = Cc[e];
             adam_update<T>(p, G[e], b, cc, F.lr, F.b1, F.b2, F.one_m_b1, F.one_m_b2, c1, c2, F.eps, F.lower);
             M[e] = p;
-            C.B[e] = b;
-            C.C[e] = cc;
+            Bc[e] = b;
+            Cc[e] = cc;
             G[e] = T(0);
         }
         if (j + 1 < F.tau) fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);

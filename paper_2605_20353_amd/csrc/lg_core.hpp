@@ -42,6 +42,10 @@ struct LGParams {
     uint4* entries;            // [J][entry_cap] 16-byte {key, y}
     int* hist;                 // [nb][J] entries per (bucket, workgroup)
     int* start;                // [nb][J] first entry of the bucket in the workgroup's list
+    // owner pass: mode k's row blocks use workgroups [bwg_base[k], bwg_base[k+1]),
+    // bsplits[k] per row block
+    int64_t bwg_base[kMaxModes + 1];
+    int bsplits[kMaxModes];
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -73,6 +77,37 @@ template <typename T>
 __device__ __forceinline__ void global_add(T* p, T v)
 {
     unsafeAtomicAdd(p, v);
+}
+
+// Float add into LDS as a compare-and-swap loop on the bit pattern.  The
+// native LDS float atomic (ds_add_f32) retires about one lane per three
+// clocks on gfx950, while this loop costs a few LDS integer operations per
+// wave instruction when the lanes hit distinct words (one gradient row per
+// lane group).  Lanes that collide are serialised by the hardware, so every
+// pass of the loop completes at least one of them.
+__device__ __forceinline__ void lds_add(float* p, float v)
+{
+    unsigned* u = reinterpret_cast<unsigned*>(p);
+    unsigned old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const unsigned nv = __float_as_uint(__uint_as_float(old) + v);
+        if (__hip_atomic_compare_exchange_strong(u, &old, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            break;
+    }
+}
+
+__device__ __forceinline__ void lds_add(double* p, double v)
+{
+    unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const unsigned long long nv =
+            (unsigned long long)__double_as_longlong(__longlong_as_double((long long)old) + v);
+        if (__hip_atomic_compare_exchange_strong(u, &old, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            break;
+    }
 }
 
 template <typename T>
@@ -263,7 +298,7 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                         if ((P.bucket_mask >> k) & 1u) continue;
                         const int64_t i = (int64_t)unpack(P.sc.L, key[u], k);
                         if ((P.lds_mask >> k) & 1u) {
-                            atomicAdd(priv + P.lds_off[k] + i * R + col0 + v, c);
+                            lds_add(priv + P.lds_off[k] + i * R + col0 + v, c);
                         } else {
                             global_add(P.G + (P.rowoff[k] + i) * R + col0 + v, c);
                         }

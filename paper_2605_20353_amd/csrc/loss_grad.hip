@@ -27,6 +27,8 @@
 //     sample by one 16-byte entry write and read per mode -- hardware float
 //     atomics are executed beyond the L2 at a fixed request rate, which
 //     bounds the atomic strategy at large sample counts.
+#include <cmath>
+
 #include "lg_core.hpp"
 
 namespace gcp {
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
 // modes' rows, forms y prod_{n != k} A_n[i_n, :] and adds it to the LDS copy
 // of its rows; the block is flushed to G once.
 template <typename T, int D, int LANES, int VEC>
-__global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P, int splits)
+__global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
 {
     constexpr int S = 64 / LANES;
     constexpr int U = (D == 0 || LANES < 4) ? 1 : (sizeof(T) == 4 ? 4 : 2);
@@ -155,13 +157,15 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P, int 
     const bool col_ok = col0 < R;
     const int dd = D > 0 ? D : P.sc.d;
 
-    const int b = blockIdx.x / splits;
-    const int split = blockIdx.x % splits;
-    // the bucketed mode owning bucket b: bucket_base is non-decreasing and
-    // modes that are not bucketed own an empty range
+    // the mode whose workgroup range holds this workgroup (ranges of modes
+    // that are not bucketed are empty), then its row block and split
     int k = 0;
     for (int kk = 0; kk < dd; ++kk)
-        if (P.bucket_base[kk] <= b && b < P.bucket_base[kk + 1]) k = kk;
+        if (P.bwg_base[kk] <= (int64_t)blockIdx.x && (int64_t)blockIdx.x < P.bwg_base[kk + 1]) k = kk;
+    const int splits = P.bsplits[k];
+    const int64_t local = (int64_t)blockIdx.x - P.bwg_base[k];
+    const int b = P.bucket_base[k] + (int)(local / splits);
+    const int split = (int)(local % splits);
     const int64_t r0 = (int64_t)(b - P.bucket_base[k]) << P.br_shift;
     const int64_t rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[k] - r0);
     for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) part[e] = T(0);
@@ -206,7 +210,7 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P, int 
 #pragma unroll
                     for (int kk = 0; kk < DM; ++kk)
                         if (kk < dd) c *= a[u][kk][v];
-                    atomicAdd(part + i * R + col0 + v, c);
+                    lds_add(part + i * R + col0 + v, c);
                 }
             }
         }
@@ -230,7 +234,7 @@ __global__ void k_zero(T* __restrict__ p, int64_t n, double* __restrict__ loss_o
 template <typename T>
 using LGKernel = void (*)(const LGParams<T>);
 template <typename T>
-using BAKernel = void (*)(const LGParams<T>, int);
+using BAKernel = void (*)(const LGParams<T>);
 
 // (lanes, vec) shapes built for each dtype
 #define GCP_LG_SHAPES_F32(X) \
@@ -315,6 +319,7 @@ constexpr int kLdsPrivateBudget = 96 * 1024;    // bytes of private gradient per
 constexpr int kBucketLdsBudget = 32 * 1024;     // default bytes of one row block in LDS
 constexpr int kBucketMinSamples = 1 << 16;      // automatic bucketing only at or above this n
 constexpr int kMaxBuckets = 4096;
+constexpr int kBucketWgPerCu = 8;              // owner-pass workgroups per CU aimed at
 
 template <typename T>
 static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
@@ -371,11 +376,10 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
             const int64_t elems = t->dims[k] * (int64_t)R;
             const bool fits = (lds_elems + elems) * (int64_t)sizeof(T) <= kLdsPrivateBudget;
             bool want;
-            // LDS float atomics (ds_add_f32) retire about one lane per three
-            // clocks on gfx950, far below the global atomic rate, so LDS
-            // privatisation is only used when asked for
+            // automatic: when the workgroups' final flushes are few next to
+            // the per-sample global atomic requests they replace
             if (req_lds >= 0) want = (req_lds >> k) & 1;
-            else want = false;
+            else want = fits && elems * 4 * (int64_t)cus <= n * R;
             if (want) {
                 if (!fits) return set_error(GCP_ERR_ARG, "LDS-private modes exceed %d bytes", kLdsPrivateBudget);
                 P.lds_off[k] = lds_elems;
@@ -485,15 +489,36 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (bucket_mask) {
         BAKernel<T> bk = pick_bucket_kernel<T>(d, lanes, vec);
         if (!bk) return set_error(GCP_ERR_UNSUPPORTED, "no bucket kernel for lanes = %d, vec = %d", lanes, vec);
-        int splits = (tile && tile->bucket_splits > 0) ? tile->bucket_splits
-                                                        : (int)std::max<int64_t>(1, ceil_div(2 * (int64_t)cus, nb));
-        splits = (int)std::min<int64_t>(splits, nblocks);
+        // workgroups per row block: proportional to the entries a row block
+        // of the mode expects (n * rows per block / I_k, samples uniform over
+        // the rows), aiming at kBucketWgPerCu owner workgroups per CU
+        const int64_t rows_blk = int64_t(1) << br_shift;
+        double expect_total = 0.0;
+        for (int k = 0; k < d; ++k)
+            if ((bucket_mask >> k) & 1u) expect_total += (double)n;
+        const double per_wg = std::max(1.0, expect_total / ((double)kBucketWgPerCu * cus));
+        int64_t wg = 0;
+        for (int k = 0; k < d; ++k) {
+            P.bwg_base[k] = wg;
+            P.bsplits[k] = 1;
+            if (!((bucket_mask >> k) & 1u)) continue;
+            int64_t sk;
+            if (tile && tile->bucket_splits > 0) sk = tile->bucket_splits;
+            else {
+                const double per_block = (double)n * (double)std::min<int64_t>(rows_blk, t->dims[k]) / (double)t->dims[k];
+                sk = (int64_t)std::ceil(per_block / per_wg);
+            }
+            sk = std::max<int64_t>(1, std::min<int64_t>(sk, nblocks));
+            P.bsplits[k] = (int)sk;
+            wg += (int64_t)(P.bucket_base[k + 1] - P.bucket_base[k]) * sk;
+        }
+        for (int k = d; k <= kMaxModes; ++k) P.bwg_base[k] = wg;
         const int bblock = (tile && tile->bucket_block > 0) ? tile->bucket_block : 512;
         if (bblock % 64 != 0 || bblock > 1024) return set_error(GCP_ERR_ARG, "bucket_block = %d", bblock);
         const size_t part_bytes = ((size_t)1 << br_shift) * R * sizeof(T);
         st = prepare_lds(reinterpret_cast<const void*>(bk), part_bytes, t->device);
         if (st != GCP_OK) return st;
-        hipLaunchKernelGGL(bk, dim3((unsigned)(nb * splits)), dim3(bblock), part_bytes, stream, P, splits);
+        hipLaunchKernelGGL(bk, dim3((unsigned)wg), dim3(bblock), part_bytes, stream, P);
         GCP_HIP(hipGetLastError());
     }
     return GCP_OK;

@@ -1,0 +1,90 @@
+"""Parity at the full benchmark sizes, in the launch configurations bench.py
+times.
+
+10000 x 8000 x 6000 Poisson tensor with 5e7 nonzeros, rank 32, 2^20 + 2^20
+stratified samples: every one of the 2^21 samples is checked bit for bit
+against the oracle's own draw (its sorted-tuple binary search against the
+GPU's hash table), and the whole gradient of the fused kernel -- atomic and
+row-bucketed scatter -- against the oracle's gradient on its own samples.
+
+GCP-FedAdam, 64 clients on a 4 x 4 x 4 grid over 20000 x 20000 x 2000 with
+1e5..5e6 nonzeros per client: one batched (graph-replayed) round equals one
+round of per-client launches.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_20353_amd import _lib as G
+from paper_2605_20353_amd import synth
+from paper_2605_20353_amd.fedadam import FedAdam, FedConfig
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_config2_full_size_samples_and_gradient(gpu):
+    dims, R, nnz, P, Q = [10000, 8000, 6000], 32, 50_000_000, 1 << 20, 1 << 20
+    t0 = time.time()
+    data = synth.count_tensor(dims, R, nnz, seed=2607, device=gpu)
+    t = G.SparseTensor(dims, data.coords, data.vals.to(torch.float32))
+    t.reserve(P + Q, R)
+    A = synth.init_model(dims, R, 2707, device=gpu, dtype=torch.float32)
+    sp = G.SampleParams("stratified", P, Q, seed=20353, step=3)
+    c, x, w = G.gcp_sample(t, sp)
+    Ga, La = G.gcp_loss_grad(t, sp, A, R, "poisson", tile=G.Tile(bucket_modes=0, lds_modes=0))
+    Gb, Lb = G.gcp_loss_grad(t, sp, A, R, "poisson")                     # automatic: row-bucketed
+    t.status()
+    say(f"config 2: GPU side done in {time.time() - t0:.1f} s; building the oracle's sorted index")
+    coords = data.coords.cpu().numpy()
+    vals = data.vals.to(torch.float32).double().cpu().numpy()
+    del data
+    to = oracle.SparseTensor(dims, coords, vals)
+    say(f"config 2: oracle index built at {time.time() - t0:.1f} s")
+    oc, ox, ow = oracle.sample_stratified(to, P, Q, 20353, 3)
+    np.testing.assert_array_equal(c.cpu().numpy(), oc)
+    np.testing.assert_array_equal(x.cpu().numpy(), ox.astype(np.float32))
+    np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(np.float32))
+    Go, Fo = oracle.loss_grad(dims, R, A.double().cpu().numpy(), oc, ox, ow, "poisson")
+    say(f"config 2: oracle gradient at {time.time() - t0:.1f} s")
+    Go = Go.reshape(-1, R)
+    for Gx, Lx in ((Ga, La), (Gb, Lb)):
+        g = Gx.double().cpu().numpy().reshape(-1, R)
+        off = 0
+        for n in dims:
+            err = np.linalg.norm(g[off:off + n] - Go[off:off + n]) / np.linalg.norm(Go[off:off + n])
+            assert err <= 1e-5, err
+            off += n
+        assert abs(Lx.item() - Fo) <= 1e-5 * abs(Fo)
+
+
+def test_config5_full_size_batched_equals_plain(gpu):
+    gd, grid, R = [20000, 20000, 2000], (4, 4, 4), 32
+    blocks = synth.fed_blocks(gd, grid, R, 1e5, 5e6, seed=2610, device=gpu)
+    total = sum(b.data.nnz for b in blocks)
+    assert 7e7 < total < 9.5e7
+    clients = [(G.SparseTensor(b.data.dims, b.data.coords, b.data.vals.to(torch.float32)), b.row_base)
+               for b in blocks]
+    del blocks
+    U0 = synth.init_model(gd, R, 2710, device=gpu, dtype=torch.float32)
+    cfg = FedConfig(R=R, tau=10, loss="poisson", p=1 << 16, q=1 << 16, seed=20353, lr=1e-3, meta_lr=1e-3,
+                    lower=0.0)
+    Us = {}
+    for name, kw in (("plain", dict(batched=False)), ("graph", dict(batched=True, use_graph=True))):
+        fed = FedAdam(clients, gd, U0, cfg, **kw)
+        fed.round(0)
+        fed.status()
+        Us[name] = fed.U.double().cpu().numpy()
+        say(f"config 5: {name} round done")
+        fed.close()
+    rel = np.linalg.norm(Us["graph"] - Us["plain"]) / np.linalg.norm(Us["plain"])
+    assert rel <= 1e-5, rel
+    assert np.abs(Us["graph"] - U0.double().cpu().numpy().reshape(-1)).max() > 0     # the round moved U
