@@ -210,7 +210,8 @@ gcp_status gcp_sample(gcp_tensor t, const gcp_sample_params* sp, int64_t* coords
  *                stored (identical to what gcp_sample returns for `sp`);
  *   smp != NULL: the materialised list is read instead (sp->kind and sp->p
  *                still say which entries are semi-stratified nonzeros).
- * A: device model [sum_k I_k x R], 1 <= R <= 256.  G_out: device gradient of
+ * A: device model [sum_k I_k x R]; R <= 64, or even R <= 128, or R <= 256
+ * divisible by 4 (GCP_ERR_ARG otherwise).  G_out: device gradient of
  * the same shape (may be NULL with GCP_LOSS_ONLY).  loss_out: device double
  * receiving F~ = sum_s w_s f(x_s, m_s) (NULL = not computed).  Unless
  * GCP_ACCUMULATE is set, G_out and *loss_out are overwritten.  tile: launch
@@ -273,7 +274,10 @@ typedef struct gcp_fed_desc {
     int32_t lanes;            /* lane shape of the gradient part, 0 = default    */
     int32_t vec;
     int32_t max_attempts;     /* rejection attempts per zero sample, <= 0 = 64   */
-    int32_t reserved;
+    int32_t lds_modes;        /* batched: bitmask of modes whose client gradient
+                                 is accumulated in each workgroup's LDS and
+                                 flushed once per local step; -1 = automatic
+                                 (modes whose largest client block fits), 0 = none */
     int64_t p;                /* nonzero samples per client and local step       */
     int64_t q;                /* zero samples per client and local step          */
     uint64_t seed;

@@ -125,18 +125,26 @@ def tune_fedadam(fed: FedAdam, candidates=None, rounds: int = 1, warmup: int = 1
 # ------------------------------------------------------- sampled gradient --
 
 def loss_grad_candidates(R: int, dtype, reserved: bool):
-    out = []
-    base = [(0, 0)]
-    if R == 32:
-        base = [(32, 1), (16, 2)]
-    for lanes, vec in base:
-        for block in (256, 512):
-            out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=0, bucket_modes=0))
-            if reserved:
-                for spb in (2048, 4096):
-                    for splits in (0, 8):
-                        out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=0, bucket_modes=-1,
-                                          bucket_block_samples=spb, bucket_splits=splits))
+    """The library's automatic choice, then the atomic scatter with one
+    column per lane, then (with a reserved workspace) the row-bucketed
+    scatter over a few lane shapes, workgroup sizes and owner-pass splits."""
+    out = [G.Tile()]
+    out.append(G.Tile(lds_modes=0, bucket_modes=0))
+    if reserved:
+        wide = 4 if dtype == torch.float32 else 2
+        shapes = []
+        for vec in (wide, 2):
+            if R % vec == 0 and (vec, R // vec) not in [(v, R // v) for v, _ in shapes]:
+                lanes = 2
+                while lanes * vec < R:
+                    lanes *= 2
+                if lanes <= 64:
+                    shapes.append((vec, lanes))
+        for vec, lanes in shapes:
+            for block in (256, 512):
+                for splits in (0, 32):
+                    out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=-1, bucket_modes=-1,
+                                      bucket_splits=splits))
     return out
 
 

@@ -23,6 +23,7 @@ namespace gcp {
 
 constexpr uint32_t kStatusBarrier = 4u;
 constexpr long kSpinLimit = 1L << 22;
+constexpr int kFedLdsBudget = 64 * 1024;   // bytes of private client gradient per workgroup
 
 template <typename T>
 struct FedClientDev {
@@ -52,6 +53,7 @@ struct FedArgs {
     const int* cov_client;
     const int* cov_lrow;           // the row's index in the client's model
     T* const* Mptrs;               // per client model
+    int staging_bytes;             // LDS before the private gradient copies
 };
 
 __device__ __forceinline__ void fed_barrier(int* ctr, int target, uint32_t* status)
@@ -99,9 +101,11 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
     uint64_t* skey = reinterpret_cast<uint64_t*>(smem) + wave * 64;
     T* sx = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * 8) + wave * 64;
     T* sw = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * (8 + sizeof(T))) + wave * 64;
+    T* priv = reinterpret_cast<T*>(smem + F.staging_bytes);
     const int64_t round = *F.round;
     const int64_t tid = (int64_t)w * blockDim.x + threadIdx.x;
     const int64_t nthreads = (int64_t)F.W * blockDim.x;
+    const int dd = D > 0 ? D : P.sc.d;
     int arrivals = 0;
 
     // M_c <- the client's rows of the server model
@@ -112,9 +116,27 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
     for (int j = 0; j < F.tau; ++j) {
         const uint64_t step = (uint64_t)(round * F.tau + j);
         double lacc = 0.0;
+        if (P.lds_mask) {
+            for (int64_t e = threadIdx.x; e < P.lds_elems; e += blockDim.x) priv[e] = T(0);
+            __syncthreads();
+        }
         for (int64_t chunk = (int64_t)w * nwaves + wave; chunk < P.nchunks; chunk += (int64_t)F.W * nwaves)
-            lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, nullptr, nullptr, nullptr, 0, false, T(1),
+            lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, nullptr, nullptr, 0, false, T(1),
                                           lacc, step);
+        if (P.lds_mask) {
+            // flush this workgroup's share of the small modes' gradient once
+            __syncthreads();
+            for (int k = 0; k < dd; ++k) {
+                if (!((P.lds_mask >> k) & 1u)) continue;
+                const int64_t elems = P.sc.L.dims[k] * (int64_t)P.R;
+                T* dst = G + P.rowoff[k] * P.R;
+                const T* src = priv + P.lds_off[k];
+                for (int64_t e = threadIdx.x; e < elems; e += blockDim.x) {
+                    const T v = src[e];
+                    if (v != T(0)) global_add(dst + e, v);
+                }
+            }
+        }
         fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
         const int64_t t = round * F.tau + j + 1;
         const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
@@ -212,6 +234,7 @@ struct gcp_fed_s {
     unsigned char args[sizeof(FedArgs<double>)] = {};   // FedArgs<T> for the tensor dtype
     const void* client_kernel = nullptr;
     size_t client_lds = 0;
+    size_t lds_bytes = 0;          // private gradient copies of the batched kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -252,11 +275,27 @@ static gcp_status fed_build(gcp_fed_s* f)
                 ++fill[g];
             }
     }
-    gcp_tile tile{};
-    tile.lanes = f->lanes;
-    tile.vec = f->vec;
-    tile.lds_modes = 0;
-    tile.bucket_modes = 0;
+    // small modes of the batched kernel accumulate in LDS (per workgroup and
+    // local step) when the largest client block of the mode fits the budget
+    uint32_t lds_mask = 0;
+    int64_t lds_max_elems = 0;
+    if (D.batched && D.lds_modes != 0) {
+        int64_t used = 0;
+        for (int k = 0; k < d; ++k) {
+            int64_t mx = 0;
+            for (int c = 0; c < K; ++c) mx = std::max<int64_t>(mx, f->clients[c].tensor->dims[k]);
+            const int64_t bytes = mx * R * (int64_t)sizeof(T);
+            const bool want = D.lds_modes > 0 ? ((D.lds_modes >> k) & 1) : true;
+            if (want && used + bytes <= kFedLdsBudget) {
+                lds_mask |= 1u << k;
+                used += bytes;
+            } else if (D.lds_modes > 0 && want) {
+                return set_error(GCP_ERR_ARG, "LDS-private mode %d does not fit in %d bytes", k, kFedLdsBudget);
+            }
+        }
+        lds_max_elems = used / (int64_t)sizeof(T);
+    }
+    f->lds_bytes = (size_t)lds_max_elems * sizeof(T);
     for (int c = 0; c < K; ++c) {
         const gcp_fed_client& cl = f->clients[c];
         const gcp_tensor_s* t = cl.tensor;
@@ -280,6 +319,15 @@ static gcp_status fed_build(gcp_fed_s* f)
         h.P.loss = D.loss;
         for (int k = 0; k < kMaxModes; ++k) h.P.rowoff[k] = k < d ? t->rowoff[k] : t->rowoff[d];
         for (int k = 0; k <= kMaxModes; ++k) h.P.bucket_base[k] = 0;
+        h.P.lds_mask = lds_mask;
+        int64_t off = 0;
+        for (int k = 0; k < d; ++k) {
+            if ((lds_mask >> k) & 1u) {
+                h.P.lds_off[k] = off;
+                off += t->dims[k] * R;
+            }
+        }
+        h.P.lds_elems = off;
         h.B = (T*)cl.B;
         h.C = (T*)cl.C;
         h.nparams = t->rowoff[d] * R;
@@ -341,16 +389,26 @@ static gcp_status fed_build(gcp_fed_s* f)
     memcpy(f->args, &a, sizeof(a));
 
     if (D.batched) {
+        gcp_status st = GCP_OK;
         FedKernel<T> kern = nullptr;
         if (d == 3) kern = pick_fed<T, 3>(f->lanes, f->vec);
         else kern = pick_fed<T, 0>(f->lanes, f->vec);
         if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "batched lane shape lanes = %d, vec = %d not built", f->lanes,
                                     f->vec);
         f->client_kernel = reinterpret_cast<const void*>(kern);
-        f->client_lds = (size_t)(f->block / 64) * 64 * (8 + 2 * sizeof(T));
+        const size_t staging = (size_t)(f->block / 64) * 64 * (8 + 2 * sizeof(T));
+        f->client_lds = staging + f->lds_bytes;
+        reinterpret_cast<FedArgs<T>*>(f->args)->staging_bytes = (int)staging;
+        st = prepare_lds(f->client_kernel, f->client_lds, f->device);
+        if (st != GCP_OK) return st;
         int per_cu = 0;
         GCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f->client_kernel, f->block, f->client_lds));
         const int64_t resident = (int64_t)per_cu * device_cu_count(f->device);
+        if (D.workgroups_per_client <= 0) {
+            // automatic: as many workgroups per client as stay resident, <= 16
+            f->W = (int)std::max<int64_t>(1, std::min<int64_t>(16, resident / K));
+            reinterpret_cast<FedArgs<T>*>(f->args)->W = f->W;
+        }
         if ((int64_t)K * f->W > resident)
             return set_error(GCP_ERR_UNSUPPORTED,
                              "%d clients x %d workgroups exceed the %lld workgroups the GPU holds at once", K, f->W,
@@ -385,7 +443,7 @@ static gcp_status fed_round_plain(gcp_fed_s* f, int64_t round, hipStream_t strea
     gcp_tile tile{};
     tile.lanes = f->lanes;
     tile.vec = f->vec;
-    tile.lds_modes = 0;
+    tile.lds_modes = -1;       // the per-launch automatic choice
     tile.bucket_modes = 0;
     for (int j = 0; j < D.tau; ++j) {
         for (int c = 0; c < D.nclients; ++c) {

@@ -168,13 +168,21 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
     const int split = (int)(local % splits);
     const int64_t r0 = (int64_t)(b - P.bucket_base[k]) << P.br_shift;
     const int64_t rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[k] - r0);
+    const int64_t j0 = P.nblocks * split / splits, j1 = P.nblocks * (split + 1) / splits;
+    // this row block's segment counts and starts for workgroups [j0, j1),
+    // staged once in LDS after the row block
+    int* seg_cnt = reinterpret_cast<int*>(smem + (((size_t)rows * R * sizeof(T) + 15) & ~(size_t)15));
+    int* seg_start = seg_cnt + (j1 - j0);
     for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) part[e] = T(0);
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+        seg_cnt[j - j0] = P.hist[(int64_t)b * P.nblocks + j];
+        seg_start[j - j0] = P.start[(int64_t)b * P.nblocks + j];
+    }
     __syncthreads();
 
-    const int64_t j0 = P.nblocks * split / splits, j1 = P.nblocks * (split + 1) / splits;
     for (int64_t j = j0 + wave; j < j1; j += nwaves) {
-        const int cnt = P.hist[(int64_t)b * P.nblocks + j];
-        const uint4* seg = P.entries + j * P.entry_cap + P.start[(int64_t)b * P.nblocks + j];
+        const int cnt = seg_cnt[j - j0];
+        const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
         for (int base = 0; base < cnt; base += S * U) {
             uint64_t key[U];
             T y[U];
@@ -307,12 +315,30 @@ static BAKernel<T> pick_bucket_kernel(int d, int lanes, int vec)
 template <typename T>
 static void default_shape(int R, int& lanes, int& vec)
 {
-    const int vmax = sizeof(T) == 4 ? 4 : 2;
+    const int vmax = 4;
     vec = 1;
     while (vec < vmax && R > 64 * vec && R % (2 * vec) == 0) vec *= 2;
     const int need = (R + vec - 1) / vec;
     lanes = 8;
     while (lanes < need && lanes < 64) lanes <<= 1;
+}
+
+// Widest vector that divides R (4 columns per lane in float32, 2 in
+// float64), then the fewest power-of-two lanes covering R.
+template <typename T>
+static void wide_shape(int R, int& lanes, int& vec)
+{
+    const int vmax = sizeof(T) == 4 ? 4 : 2;
+    vec = 1;
+    while (vec < vmax && R % (2 * vec) == 0) vec *= 2;
+    if (vec == 1) {                      // nothing to gain
+        default_shape<T>(R, lanes, vec);
+        return;
+    }
+    const int need = (R + vec - 1) / vec;
+    lanes = vec == 4 ? 2 : 4;            // the narrowest shapes built
+    while (lanes < need && lanes < 64) lanes <<= 1;
+    if (lanes * vec < R) default_shape<T>(R, lanes, vec);
 }
 
 constexpr int kLdsPrivateBudget = 96 * 1024;    // bytes of private gradient per workgroup
@@ -343,26 +369,6 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (smp && (!smp->coords || !smp->x || !smp->w) && n > 0)
         return set_error(GCP_ERR_ARG, "materialised sample list has a NULL array");
 
-    int lanes = 0, vec = 0;
-    default_shape<T>(R, lanes, vec);
-    if (tile && tile->vec > 0) vec = tile->vec;
-    if (tile && tile->lanes > 0) lanes = tile->lanes;
-    else if (tile && tile->vec > 0) {
-        const int need = (R + vec - 1) / vec;
-        lanes = 2;
-        while (lanes < need && lanes < 64) lanes <<= 1;
-    }
-    if (R % vec != 0) return set_error(GCP_ERR_ARG, "vec = %d does not divide R = %d", vec, R);
-    if (lanes * vec < R) return set_error(GCP_ERR_ARG, "lanes*vec = %d < R = %d", lanes * vec, R);
-    const int src = smp ? 1 : 0;
-    if (sizeof(T) == 8 && t->d != 3 && t->d != 4 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
-        lanes = 32;
-        vec = 2;
-    }
-    LGKernel<T> kern = pick_kernel<T>(t->d, src, lanes, vec);
-    if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "tile lanes = %d, vec = %d not built for this dtype", lanes, vec);
-    const uintptr_t align = (uintptr_t)vec * sizeof(T);
-    if (((uintptr_t)A % align) != 0) return set_error(GCP_ERR_ARG, "A is not %d-byte aligned", (int)align);
     const int d = t->d;
     const int cus = device_cu_count(t->device);
 
@@ -414,8 +420,37 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
             return set_error(GCP_ERR_ARG, "workspace reserved by gcp_tensor_reserve is too small for this call");
     }
 
+    // lane shape: one column per lane while any mode scatters with global
+    // atomics (one request per row); otherwise the widest vector, which
+    // spreads each sample over the fewest lanes and so cuts the per-sample
+    // instructions (the LDS and bucketed scatters issue no global atomics)
+    const uint32_t all_modes = (1u << d) - 1;
+    const bool no_global_atomics = loss_only || ((lds_mask | bucket_mask) == all_modes);
+    int lanes = 0, vec = 0;
+    default_shape<T>(R, lanes, vec);
+    if (no_global_atomics) wide_shape<T>(R, lanes, vec);
+    if (tile && tile->vec > 0) vec = tile->vec;
+    if (tile && tile->lanes > 0) lanes = tile->lanes;
+    else if (tile && tile->vec > 0) {
+        const int need = (R + vec - 1) / vec;
+        lanes = 2;
+        while (lanes < need && lanes < 64) lanes <<= 1;
+    }
+    if (R % vec != 0) return set_error(GCP_ERR_ARG, "vec = %d does not divide R = %d", vec, R);
+    if (lanes * vec < R) return set_error(GCP_ERR_ARG, "lanes*vec = %d < R = %d", lanes * vec, R);
+    const int src = smp ? 1 : 0;
+    if (sizeof(T) == 8 && t->d != 3 && t->d != 4 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
+        lanes = 32;
+        vec = 2;
+    }
+    LGKernel<T> kern = pick_kernel<T>(t->d, src, lanes, vec);
+    if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "tile lanes = %d, vec = %d not built for this dtype", lanes, vec);
+    const uintptr_t align = (uintptr_t)vec * sizeof(T);
+    if (((uintptr_t)A % align) != 0) return set_error(GCP_ERR_ARG, "A is not %d-byte aligned", (int)align);
+
     int block = 256;
     if (lds_mask) block = 1024;
+    else if (bucket_mask) block = 512;
     if (tile && tile->block > 0) {
         if (tile->block % 64 != 0 || tile->block > 1024) return set_error(GCP_ERR_ARG, "block = %d", tile->block);
         block = tile->block;
@@ -515,7 +550,10 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
         for (int k = d; k <= kMaxModes; ++k) P.bwg_base[k] = wg;
         const int bblock = (tile && tile->bucket_block > 0) ? tile->bucket_block : 512;
         if (bblock % 64 != 0 || bblock > 1024) return set_error(GCP_ERR_ARG, "bucket_block = %d", bblock);
-        const size_t part_bytes = ((size_t)1 << br_shift) * R * sizeof(T);
+        int64_t max_segs = 0;
+        for (int k = 0; k < d; ++k)
+            if ((bucket_mask >> k) & 1u) max_segs = std::max<int64_t>(max_segs, ceil_div(nblocks, P.bsplits[k]));
+        const size_t part_bytes = ((((size_t)1 << br_shift) * R * sizeof(T) + 15) & ~(size_t)15) + 8 * (size_t)max_segs;
         st = prepare_lds(reinterpret_cast<const void*>(bk), part_bytes, t->device);
         if (st != GCP_OK) return st;
         hipLaunchKernelGGL(bk, dim3((unsigned)wg), dim3(bblock), part_bytes, stream, P);
