@@ -47,8 +47,8 @@ P = Q = 1 << 20
 DATA_SEED = 2607
 SAMPLE_SEED = 20353
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loss_grad_cfg2_traffic.json")
-KERNEL_SOURCES = ["paper_2605_20353_amd/csrc/loss_grad.hip", "paper_2605_20353_amd/csrc/sampling.hpp",
-                  "paper_2605_20353_amd/csrc/gcp_internal.hpp"]
+KERNEL_SOURCES = ["paper_2605_20353_amd/csrc/loss_grad.hip", "paper_2605_20353_amd/csrc/lg_core.hpp",
+                  "paper_2605_20353_amd/csrc/sampling.hpp", "paper_2605_20353_amd/csrc/gcp_internal.hpp"]
 
 
 def log(msg: str) -> None:
@@ -272,7 +272,8 @@ def main():
     traffic = measured_traffic()
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_loss_grad (fused sampled loss/gradient)",
+            "kernel": "gcp_loss_grad: k_loss_grad (sampling, model values, loss derivative, scatter or "
+                      "row-block sort) + k_bucket_accum (row-block owner pass) when bucketed",
             "kernel_ms_mean": round(kmean, 5), "kernel_ms_median": round(float(np.median(kms)), 5),
             "algorithmic_bytes_per_launch": alg}
     log(f"step {ms_per_step:.4f} ms, {value:.4g} samples/s; loss_grad kernel {kmean:.4f} ms "
