@@ -229,6 +229,37 @@ def run_cpu_baseline(data, A_init: np.ndarray, steps: int):
                       f"{dt:.1f} s"}
 
 
+def fused_experiment(dev, sizes, iters: int):
+    """Fused vs non-fused sampled gradient on a synthetic tensor shaped like
+    the paper's arXiv tensor (172 x 25000 x 300, 3e7 nonzeros, Poisson), with
+    semi-stratified samples (the same number of nonzero and zero samples) swept:
+    fused = one gcp_loss_grad that draws the samples in-kernel; non-fused =
+    gcp_sample materialising the sampled tensor, then gcp_loss_grad reading
+    it.  Rank 32 (the paper does not state the rank of this experiment)."""
+    dims, R = [172, 25000, 300], 32
+    log("fused experiment: generating 172x25000x300 with 3e7 nonzeros")
+    data = synth.count_tensor(dims, R, 30_000_000, seed=2612, device=dev)
+    t = G.SparseTensor(dims, data.coords, data.vals.to(torch.float32))
+    del data
+    t.reserve(2 * max(sizes), R)
+    A = synth.init_model(dims, R, 2712, device=dev, dtype=torch.float32)
+    Gr = torch.zeros_like(A)
+    rows = []
+    for s in sizes:
+        sp = G.SampleParams("semi_stratified", s, s, seed=SAMPLE_SEED, step=0)
+        fused = _time_ms(lambda: G.gcp_loss_grad(t, sp, A, R, "poisson", G=Gr, want_loss=False), iters, 3)
+
+        def nonfused():
+            smp = G.gcp_sample(t, sp)
+            G.gcp_loss_grad(t, sp, A, R, "poisson", G=Gr, want_loss=False, samples=smp)
+
+        nf = _time_ms(nonfused, iters, 3)
+        rows.append({"samples": 2 * s, "fused_ms": fused, "nonfused_ms": nf, "ratio": nf / fused})
+        log(f"fused experiment: {2 * s} samples: fused {fused:.3f} ms, non-fused {nf:.3f} ms, ratio {nf / fused:.2f}")
+    t.status()
+    return {"workload": "172x25000x300 Poisson, 3e7 nonzeros, rank 32 FP32, semi-stratified p = q", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,7 +273,13 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times, so that "
                          "rocprofv3's FETCH_SIZE / WRITE_SIZE can be calibrated against known bytes")
+    ap.add_argument("--fused-experiment", action="store_true",
+                    help="only run the fused vs non-fused sampled-gradient comparison and print its JSON")
     args = ap.parse_args()
+    if args.fused_experiment:
+        out = fused_experiment(torch.device("cuda:0"), [1 << k for k in (14, 16, 18, 20, 22)], 20)
+        print(json.dumps(out))
+        return
     if args.copy_calibration:
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         y = torch.empty_like(x)

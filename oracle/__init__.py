@@ -329,3 +329,51 @@ def fedadam_round(clients, global_dims, R: int, U: np.ndarray, Bs: np.ndarray, C
     adam(U, D.reshape(-1), Bs, Cs, server_t, server_ap.lr, server_ap.beta1, server_ap.beta2,
          server_ap.eps, server_ap.lower)
     return server_t
+
+
+def objective(t: SparseTensor, R: int, A, loss, p: int, q: int, seed: int, step: int = 0, client: int = 0,
+              semi: bool = False) -> float:
+    """Sampled objective F~ on the stratified sample set (seed, step, client)."""
+    coords, x, w = sample_stratified(t, p, q, seed, step, client, semi=semi)
+    _, F = loss_grad(t.dims, R, A, coords, x, w, loss, n_semi=p if semi else 0)
+    return F
+
+
+def gcp_adam_epochs(t: SparseTensor, R: int, A0, loss, p: int, q: int, obj_p: int, obj_q: int,
+                    iters_per_epoch: int, max_epochs: int, lr: float, decay: float, max_fails: int,
+                    seed: int, obj_client: int, ap: AdamParams):
+    """GCP-Adam epochs with the restore-and-decay safeguard, written out on the
+    oracle's routines: each epoch runs iters_per_epoch sampled-gradient Adam
+    iterations (iteration number = RNG step, counted over all epochs, accepted
+    or not); the objective is estimated on the fixed set (seed, step 0,
+    obj_client); an epoch that does not lower it is undone and the rate is
+    multiplied by decay; the run stops after max_fails undone epochs.
+    Returns (A, objectives of accepted epochs with the initial one first,
+    rates per epoch, fails)."""
+    A = _f64(A0).reshape(-1).copy()
+    B = np.zeros_like(A)
+    Cm = np.zeros_like(A)
+    f_prev = objective(t, R, A, loss, obj_p, obj_q, seed, 0, obj_client)
+    objs, rates = [f_prev], []
+    rate, tcount, it, fails = lr, 0, 0, 0
+    for _ in range(max_epochs):
+        saved = (A.copy(), B.copy(), Cm.copy(), tcount)
+        for _ in range(iters_per_epoch):
+            coords, x, w = sample_stratified(t, p, q, seed, it, 0)
+            G, _ = loss_grad(t.dims, R, A, coords, x, w, loss)
+            tcount += 1
+            it += 1
+            adam(A, G, B, Cm, tcount, rate, ap.beta1, ap.beta2, ap.eps, ap.lower)
+        f = objective(t, R, A, loss, obj_p, obj_q, seed, 0, obj_client)
+        rates.append(rate)
+        if f < f_prev:
+            f_prev = f
+            objs.append(f)
+        else:
+            A[:], B[:], Cm[:] = saved[0], saved[1], saved[2]
+            tcount = saved[3]
+            rate *= decay
+            fails += 1
+            if fails >= max_fails:
+                break
+    return A, objs, rates, fails

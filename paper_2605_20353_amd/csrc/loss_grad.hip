@@ -411,7 +411,14 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
             }
         }
         for (int k = d; k <= kMaxModes; ++k) P.bucket_base[k] = nb;
-        spb = (tile && tile->bucket_block_samples > 0) ? tile->bucket_block_samples : 2048;
+        if (tile && tile->bucket_block_samples > 0) {
+            spb = tile->bucket_block_samples;
+        } else {
+            // 2048 samples per workgroup, fewer when that leaves under two
+            // workgroups per CU
+            spb = 2048;
+            while (spb > 512 && ceil_div(n, spb) < 2 * (int64_t)cus) spb /= 2;
+        }
         if (spb % 64 != 0 || spb < 512 || spb > 8192) return set_error(GCP_ERR_ARG, "bucket_block_samples = %d", spb);
         nblocks = ceil_div(n, spb);
         if (nb > kMaxBuckets) return set_error(GCP_ERR_UNSUPPORTED, "%d row blocks exceed %d", nb, kMaxBuckets);
