@@ -82,6 +82,26 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
+TILE_FIELDS = ("lanes", "vec", "block", "grid", "lds_modes", "bucket_modes", "bucket_lds_bytes",
+               "bucket_block_samples", "bucket_splits", "bucket_block")
+
+
+def parse_tile(spec: str) -> G.Tile:
+    if spec == "default":
+        return G.Tile()
+    kw = {}
+    for part in spec.split(","):
+        k, _, v = part.partition("=")
+        if k.strip() not in TILE_FIELDS:
+            raise SystemExit(f"--tile: unknown field {k!r}; fields are {', '.join(TILE_FIELDS)}")
+        kw[k.strip()] = int(v)
+    return G.Tile(**kw)
+
+
+def tile_dict(tile: G.Tile) -> dict:
+    return {f: getattr(tile, f) for f in TILE_FIELDS}
+
+
 def build_workload(dev):
     log(f"generating {DIMS} with {NNZ} nonzeros (rank-{RANK} gamma model) on {dev}")
     t0 = time.time()
@@ -275,6 +295,10 @@ def main():
                          "rocprofv3's FETCH_SIZE / WRITE_SIZE can be calibrated against known bytes")
     ap.add_argument("--fused-experiment", action="store_true",
                     help="only run the fused vs non-fused sampled-gradient comparison and print its JSON")
+    ap.add_argument("--tile", default="",
+                    help="fixed sampled-gradient tile instead of the autotuned one, as comma-separated "
+                         "key=value pairs of gcp_tile fields (e.g. lanes=8,vec=4,block=256,bucket_block=1024); "
+                         "'default' = the library's automatic choice")
     args = ap.parse_args()
     if args.fused_experiment:
         out = fused_experiment(torch.device("cuda:0"), [1 << k for k in (14, 16, 18, 20, 22)], 20)
@@ -297,8 +321,12 @@ def main():
     data, t, A = build_workload(dev)
     A0 = A.cpu().numpy().copy()
     sp0 = G.SampleParams("stratified", P, Q, seed=SAMPLE_SEED, step=0)
-    tile = autotune.tune_loss_grad(t, sp0, A, RANK, "poisson", reps=10)
-    log(f"autotuned sampled-gradient tile: {tile}")
+    if args.tile:
+        tile = parse_tile(args.tile)
+        log(f"fixed sampled-gradient tile: {tile}")
+    else:
+        tile = autotune.tune_loss_grad(t, sp0, A, RANK, "poisson", reps=10)
+        log(f"autotuned sampled-gradient tile: {tile}")
     log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
     wall, kms, loss_est, n_params = run_gpu(t, A, args.steps, args.warmup, tile)
     ms_per_step = 1e3 * wall / args.steps
@@ -315,9 +343,8 @@ def main():
             "algorithmic_bytes_per_launch": alg}
     log(f"step {ms_per_step:.4f} ms, {value:.4g} samples/s; loss_grad kernel {kmean:.4f} ms "
         f"-> {achieved:.0f} GB/s algorithmic")
-    roof["tile"] = {"lanes": tile.lanes, "vec": tile.vec, "block": tile.block, "lds_modes": tile.lds_modes,
-                    "bucket_modes": tile.bucket_modes, "bucket_block_samples": tile.bucket_block_samples,
-                    "bucket_splits": tile.bucket_splits}
+    roof["tile"] = tile_dict(tile)
+    roof["tile_source"] = "fixed" if args.tile else "autotuned"
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(data, A0, args.cpu_steps)

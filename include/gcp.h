@@ -133,8 +133,11 @@ typedef struct gcp_tile {
                                      power of two); 0 = 32768, min 8192     */
     int32_t bucket_block_samples; /* samples sorted per workgroup, multiple
                                      of 64 in [512, 8192]; 0 = 2048          */
-    int32_t bucket_splits;        /* workgroups per row block; 0 = auto     */
-    int32_t bucket_block;         /* threads per row-block workgroup; 0 = 512 */
+    int32_t bucket_splits;        /* workgroups per row block (each reads
+                                     ceil(J / bucket_splits) of the J sort
+                                     segments); 0 = auto                    */
+    int32_t bucket_block;         /* threads per row-block workgroup, multiple
+                                     of 64 up to 1024; 0 = 1024             */
 } gcp_tile;
 
 /* gcp_loss_grad flags */

@@ -127,7 +127,8 @@ def tune_fedadam(fed: FedAdam, candidates=None, rounds: int = 1, warmup: int = 1
 def loss_grad_candidates(R: int, dtype, reserved: bool):
     """The library's automatic choice, then the atomic scatter with one
     column per lane, then (with a reserved workspace) the row-bucketed
-    scatter over a few lane shapes, workgroup sizes and owner-pass splits."""
+    scatter over a few lane shapes, workgroup sizes, owner-pass workgroup
+    sizes and splits."""
     out = [G.Tile()]
     out.append(G.Tile(lds_modes=0, bucket_modes=0))
     if reserved:
@@ -142,9 +143,9 @@ def loss_grad_candidates(R: int, dtype, reserved: bool):
                     shapes.append((vec, lanes))
         for vec, lanes in shapes:
             for block in (256, 512):
-                for splits in (0, 32):
+                for bblock, splits in ((1024, 0), (512, 0), (512, 32), (1024, 32)):
                     out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=-1, bucket_modes=-1,
-                                      bucket_splits=splits))
+                                      bucket_splits=splits, bucket_block=bblock))
     return out
 
 

@@ -43,9 +43,10 @@ struct LGParams {
     int* hist;                 // [nb][J] entries per (bucket, workgroup)
     int* start;                // [nb][J] first entry of the bucket in the workgroup's list
     // owner pass: mode k's row blocks use workgroups [bwg_base[k], bwg_base[k+1]),
-    // bsplits[k] per row block
+    // bsplits[k] per row block, each reading bsegs[k] consecutive segments
     int64_t bwg_base[kMaxModes + 1];
     int bsplits[kMaxModes];
+    int bsegs[kMaxModes];
 };
 
 __device__ __forceinline__ void wave_sync()
@@ -169,6 +170,21 @@ __device__ inline void wave_exclusive_scan(const int* cnt, int* off, int n, int 
     }
 }
 
+// Samples per lane group whose factor-row gathers are issued together.  It
+// must divide LANES: a pass covers samples it*S+g .. (it+U-1)*S+g of the
+// wave's 64 staged samples, so a U that does not divide LANES would read past
+// the staging slice on the last pass.
+#ifndef GCP_UNROLL_WIDE
+#define GCP_UNROLL_WIDE 2
+#endif
+template <typename T, int D, int LANES, int VEC>
+constexpr int samples_in_flight()
+{
+    constexpr int U = (D == 0 || LANES < 4) ? 1 : sizeof(T) == 8 ? 2 : VEC == 4 ? GCP_UNROLL_WIDE : 4;
+    static_assert(U >= 1 && LANES % U == 0, "samples in flight must divide the lanes per sample");
+    return U;
+}
+
 // One chunk of 64 samples: phase 1 (one lane per sample: draw or read the
 // sample, stage it in the wave's LDS slice) and phase 2 (LANES lanes per
 // sample: gather rows, model value, loss derivative, scatter).  Shared by the
@@ -179,8 +195,7 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                                          T scale, double& lacc, uint64_t step)
 {
     constexpr int S = 64 / LANES;                  // samples per pass
-    // samples per lane group whose row gathers are issued together
-    constexpr int U = (D == 0 || LANES < 4) ? 1 : (sizeof(T) == 4 ? 4 : 2);
+    constexpr int U = samples_in_flight<T, D, LANES, VEC>();
     constexpr int DM = D > 0 ? D : kMaxModes;
     const int dd = D > 0 ? D : P.sc.d;
     const int R = P.R;

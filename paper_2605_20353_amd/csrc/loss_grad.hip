@@ -145,8 +145,9 @@ template <typename T, int D, int LANES, int VEC>
 __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
 {
     constexpr int S = 64 / LANES;
-    constexpr int U = (D == 0 || LANES < 4) ? 1 : (sizeof(T) == 4 ? 4 : 2);
+    constexpr int U = samples_in_flight<T, D, LANES, VEC>();
     constexpr int DM = D > 0 ? D : kMaxModes;
+    static_assert(VEC == 1 || VEC == 2 || VEC == 4, "columns per lane");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     T* part = reinterpret_cast<T*>(smem);
     const int nwaves = blockDim.x >> 6;
@@ -168,7 +169,10 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
     const int split = (int)(local % splits);
     const int64_t r0 = (int64_t)(b - P.bucket_base[k]) << P.br_shift;
     const int64_t rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[k] - r0);
-    const int64_t j0 = P.nblocks * split / splits, j1 = P.nblocks * (split + 1) / splits;
+    // whole segments per workgroup (the host makes it a multiple of the
+    // waves per workgroup); the last split takes the remainder
+    const int64_t j0 = (int64_t)split * P.bsegs[k];
+    const int64_t j1 = std::min<int64_t>(P.nblocks, j0 + P.bsegs[k]);
     // this row block's segment counts and starts for workgroups [j0, j1),
     // staged once in LDS after the row block
     int* seg_cnt = reinterpret_cast<int*>(smem + (((size_t)rows * R * sizeof(T) + 15) & ~(size_t)15));
@@ -183,6 +187,13 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
     for (int64_t j = j0 + wave; j < j1; j += nwaves) {
         const int cnt = seg_cnt[j - j0];
         const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
+        // entries of the next pass are loaded while this pass gathers rows
+        uint4 nxt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = u * S + g;
+            nxt[u] = e < cnt ? seg[e] : make_uint4(0, 0, 0, 0);
+        }
         for (int base = 0; base < cnt; base += S * U) {
             uint64_t key[U];
             T y[U];
@@ -191,7 +202,9 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
             for (int u = 0; u < U; ++u) {
                 const int e = base + u * S + g;
                 const bool valid = e < cnt;
-                uint4 ent = valid ? seg[e] : make_uint4(0, 0, 0, 0);
+                const uint4 ent = nxt[u];
+                const int en = e + S * U;
+                nxt[u] = en < cnt ? seg[en] : make_uint4(0, 0, 0, 0);
                 key[u] = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
                 y[u] = valid ? entry_y<T>(ent) : T(0);
 #pragma unroll
@@ -212,13 +225,20 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
                 const int e = base + u * S + g;
                 if (e >= cnt || !col_ok) continue;
                 const int64_t i = (int64_t)unpack(P.sc.L, key[u], k) - r0;
+                T c[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
-                    T c = y[u];
+                    c[v] = y[u];
 #pragma unroll
                     for (int kk = 0; kk < DM; ++kk)
-                        if (kk < dd) c *= a[u][kk][v];
-                    lds_add(part + i * R + col0 + v, c);
+                        if (kk < dd) c[v] *= a[u][kk][v];
+                }
+                T* dst = part + i * R + col0;
+                lds_add(dst, c[0]);
+                if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
+                if constexpr (VEC > 2) {
+                    lds_add(dst + 2, c[2]);
+                    lds_add(dst + 3, c[3]);
                 }
             }
         }
@@ -531,35 +551,42 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (bucket_mask) {
         BAKernel<T> bk = pick_bucket_kernel<T>(d, lanes, vec);
         if (!bk) return set_error(GCP_ERR_UNSUPPORTED, "no bucket kernel for lanes = %d, vec = %d", lanes, vec);
+        const int bblock = (tile && tile->bucket_block > 0) ? tile->bucket_block : 1024;
+        if (bblock % 64 != 0 || bblock > 1024) return set_error(GCP_ERR_ARG, "bucket_block = %d", bblock);
+        const int bwaves = bblock / 64;
         // workgroups per row block: proportional to the entries a row block
         // of the mode expects (n * rows per block / I_k, samples uniform over
-        // the rows), aiming at kBucketWgPerCu owner workgroups per CU
+        // the rows), aiming at kBucketWgPerCu owner workgroups per CU.  Each
+        // workgroup reads a whole number of segments per wave, since its waves
+        // take its segments in turn and one wave with an extra segment would
+        // hold up the workgroup
         const int64_t rows_blk = int64_t(1) << br_shift;
         double expect_total = 0.0;
         for (int k = 0; k < d; ++k)
             if ((bucket_mask >> k) & 1u) expect_total += (double)n;
         const double per_wg = std::max(1.0, expect_total / ((double)kBucketWgPerCu * cus));
-        int64_t wg = 0;
+        int64_t wg = 0, max_segs = 0;
         for (int k = 0; k < d; ++k) {
             P.bwg_base[k] = wg;
             P.bsplits[k] = 1;
+            P.bsegs[k] = (int)nblocks;
             if (!((bucket_mask >> k) & 1u)) continue;
-            int64_t sk;
-            if (tile && tile->bucket_splits > 0) sk = tile->bucket_splits;
-            else {
+            int64_t segs;
+            if (tile && tile->bucket_splits > 0) {
+                segs = ceil_div(nblocks, (int64_t)tile->bucket_splits);
+            } else {
                 const double per_block = (double)n * (double)std::min<int64_t>(rows_blk, t->dims[k]) / (double)t->dims[k];
-                sk = (int64_t)std::ceil(per_block / per_wg);
+                const double target = std::max(1.0, std::ceil(per_block / per_wg));
+                const int64_t per_wave = std::max<int64_t>(1, std::llround((double)nblocks / (target * bwaves)));
+                segs = per_wave * bwaves;
             }
-            sk = std::max<int64_t>(1, std::min<int64_t>(sk, nblocks));
-            P.bsplits[k] = (int)sk;
-            wg += (int64_t)(P.bucket_base[k + 1] - P.bucket_base[k]) * sk;
+            segs = std::max<int64_t>(1, std::min<int64_t>(segs, nblocks));
+            P.bsegs[k] = (int)segs;
+            P.bsplits[k] = (int)ceil_div(nblocks, segs);
+            max_segs = std::max<int64_t>(max_segs, segs);
+            wg += (int64_t)(P.bucket_base[k + 1] - P.bucket_base[k]) * P.bsplits[k];
         }
         for (int k = d; k <= kMaxModes; ++k) P.bwg_base[k] = wg;
-        const int bblock = (tile && tile->bucket_block > 0) ? tile->bucket_block : 512;
-        if (bblock % 64 != 0 || bblock > 1024) return set_error(GCP_ERR_ARG, "bucket_block = %d", bblock);
-        int64_t max_segs = 0;
-        for (int k = 0; k < d; ++k)
-            if ((bucket_mask >> k) & 1u) max_segs = std::max<int64_t>(max_segs, ceil_div(nblocks, P.bsplits[k]));
         const size_t part_bytes = ((((size_t)1 << br_shift) * R * sizeof(T) + 15) & ~(size_t)15) + 8 * (size_t)max_segs;
         st = prepare_lds(reinterpret_cast<const void*>(bk), part_bytes, t->device);
         if (st != GCP_OK) return st;
