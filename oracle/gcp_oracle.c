@@ -171,18 +171,18 @@ int64_t ora_find(const ora_tensor* t, const int64_t* idx)
     return -1;
 }
 
-static double ora_cell_count(int d, const int64_t* dims)
+/* M = prod_k I_k, exact in unsigned 64-bit arithmetic (tensors of up to
+ * 2^64 - 1 cells). */
+static uint64_t ora_cell_count_u(int d, const int64_t* dims)
 {
-    int64_t M = 1;
-    for (int k = 0; k < d; ++k) M *= dims[k];
-    return (double)M;
+    uint64_t M = 1;
+    for (int k = 0; k < d; ++k) M *= (uint64_t)dims[k];
+    return M;
 }
 
-static int64_t ora_cell_count_i(int d, const int64_t* dims)
+static double ora_cell_count(int d, const int64_t* dims)
 {
-    int64_t M = 1;
-    for (int k = 0; k < d; ++k) M *= dims[k];
-    return M;
+    return (double)ora_cell_count_u(d, dims);
 }
 
 /* Stratified sampling (Sec. 3.1.1): p nonzeros drawn uniformly with
@@ -198,10 +198,10 @@ int ora_sample_stratified(const ora_tensor* t, int64_t p, int64_t q, uint64_t se
 {
     const int d = t->d;
     const int64_t N = t->nnz;
-    const int64_t M = ora_cell_count_i(d, t->dims);
-    if (p < 0 || q < 0 || (p > 0 && N == 0) || (q > 0 && !semi && N >= M)) return ORA_ERR_ARG;
+    const uint64_t M = ora_cell_count_u(d, t->dims);
+    if (p < 0 || q < 0 || (p > 0 && N == 0) || (q > 0 && !semi && (uint64_t)N >= M)) return ORA_ERR_ARG;
     const double w_nz = p > 0 ? (double)N / (double)p : 0.0;
-    const double w_z = q > 0 ? (double)(M - N) / (double)q : 0.0;
+    const double w_z = q > 0 ? (double)(M - (uint64_t)N) / (double)q : 0.0;
     uint64_t key[2] = {seed, client};
     for (int64_t s = 0; s < p; ++s) {
         uint64_t ctr[4] = {(uint64_t)s, step, ORA_STREAM_NONZERO, 0};

@@ -189,6 +189,28 @@ def test_zero_candidates_follow_counter_layout():
     assert (sw == np.prod(dims) / 4).all()
 
 
+def test_zero_weight_exact_beyond_int64_cell_counts():
+    # Amazon-shaped dimensions: M = 4821207 * 1774269 * 1805187 ~ 1.54e19 cells,
+    # above 2^63.  The zero weight (M - N) / q comes from the exact count
+    # (Python integers here), the zeros are drawn by the range map per mode and
+    # never hit a stored nonzero.
+    dims = (4821207, 1774269, 1805187)
+    M = dims[0] * dims[1] * dims[2]
+    assert (1 << 63) < M < (1 << 64)
+    rng = np.random.default_rng(5)
+    coords = np.unique(np.stack([rng.integers(0, n, 300) for n in dims], axis=1), axis=0)
+    t = oracle.SparseTensor(dims, coords, np.ones(len(coords)))
+    assert t.cells == M
+    sc, sx, sw = oracle.sample_stratified(t, 8, 64, seed=3, step=1)
+    assert (sw[8:] == float(M - len(coords)) / 64).all()
+    assert (sw[:8] == len(coords) / 8).all()
+    present = set(map(tuple, coords.tolist()))
+    for s in range(8, 72):
+        assert tuple(sc[s]) not in present and sx[s] == 0.0
+        o = oracle.philox4x64_10([s - 8, 1, 1, 0], [3, 0])
+        assert sc[s].tolist() == [oracle.range_map(int(o[k]), dims[k]) for k in range(3)]
+
+
 def test_uniform_sampling_reads_dense_values():
     dims = (3, 4, 5)
     dense = np.arange(60, dtype=np.float64) * 0.5
