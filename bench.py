@@ -161,6 +161,20 @@ def _time_ms(fn, reps: int, warmup: int) -> float:
     return 1e3 * (time.perf_counter() - t0) / reps
 
 
+def _median_ms(fn, reps: int, warmup: int) -> float:
+    """Median over reps of one call each, wall clock between device synchronisations."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(1e3 * (time.perf_counter() - t0))
+    return float(np.median(ts))
+
+
 def run_fedadam(dev, rounds: int):
     """GCP-FedAdam, 64 clients on a 4x4x4 block grid over 20000x20000x2000,
     1e5..5e6 nonzeros per client (log-uniform), rank 32 FP32, tau = 10 local
@@ -181,14 +195,14 @@ def run_fedadam(dev, rounds: int):
                        f"{nnz} nonzeros, rank 32 FP32, tau 10 x (2^16 + 2^16) samples per client",
            "nnz": nnz}
     plain = FedAdam(clients, gd, U0, cfg, batched=False)
-    out["plain_ms_per_round"] = _time_ms(lambda: plain.round(0), rounds, 1)
+    out["plain_ms_per_round"] = _median_ms(lambda: plain.round(0), rounds, 1)
     plain.status()
     plain.close()
     fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True)
     tile = autotune.tune_fedadam(fed, rounds=1, warmup=1, use_cache=False)
     out["batched_tile"] = {"workgroups_per_client": tile.workgroups_per_client, "block": tile.block,
                            "lanes": tile.lanes, "vec": tile.vec}
-    out["batched_ms_per_round"] = _time_ms(lambda: fed.round(0), rounds, 1)
+    out["batched_ms_per_round"] = _median_ms(lambda: fed.round(0), rounds, 1)
     fed.status()
     fed.close()
     out["speedup"] = out["plain_ms_per_round"] / out["batched_ms_per_round"]
@@ -223,8 +237,8 @@ def run_autograd(dev, which: str, reps: int):
         A.grad = None
         gcp_loss(A, t, R, loss, sp).backward()
 
-    ms = _time_ms(fb, reps, 2)
-    log(f"autograd {which}: {ms:.3f} ms per forward+backward")
+    ms = _median_ms(fb, reps, 3)
+    log(f"autograd {which}: {ms:.3f} ms per forward+backward (median of {reps})")
     return {"workload": desc, "ms_per_forward_backward": ms, "samples_per_s": s / (ms * 1e-3)}
 
 
@@ -280,6 +294,54 @@ def fused_experiment(dev, sizes, iters: int):
     return {"workload": "172x25000x300 Poisson, 3e7 nonzeros, rank 32 FP32, semi-stratified p = q", "rows": rows}
 
 
+def hbm_resident(dev, nnz: int, steps: int, warmup: int):
+    """The HBM-resident-factor regime: a synthetic count tensor shaped like the
+    Amazon reviews tensor (4821207 x 1774269 x 1805187; its cells need 65 key
+    bits, so the mixed-radix cell key), rank 32 FP32, so the factor, gradient
+    and moment arrays are 1.07 GB each -- far beyond the L2 and Infinity Cache
+    -- and every factor-row gather and gradient update goes to HBM.  Same step
+    as the headline benchmark: 2^20 + 2^20 stratified samples, sampled
+    gradient with the library's automatic launch shape, Adam."""
+    dims, R = [4821207, 1774269, 1805187], 32
+    log(f"hbm-resident: generating {dims} with {nnz} nonzeros (rank-{R} gamma model)")
+    t0 = time.time()
+    data = synth.count_tensor(dims, R, nnz, seed=2614, dist="gamma", device=dev)
+    gen_s = time.time() - t0
+    t = G.SparseTensor(dims, data.coords, data.vals.to(torch.float32))
+    del data
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    log(f"  generated in {gen_s:.1f} s; tensor handle {t.device_bytes() / 2**30:.1f} GiB")
+    A = synth.init_model(dims, R, 2714, dist="uniform", device=dev, dtype=torch.float32)
+    Gr, B, Cm = torch.zeros_like(A), torch.zeros_like(A), torch.zeros_like(A)
+    tile = G.Tile()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for k in range(warmup + steps):
+        sp = G.SampleParams("stratified", P, Q, seed=SAMPLE_SEED, step=k)
+        if k >= warmup:
+            ev[k - warmup][0].record()
+        G.gcp_loss_grad(t, sp, A, R, "poisson", G=Gr, accumulate=True, want_loss=False, tile=tile)
+        if k >= warmup:
+            ev[k - warmup][1].record()
+        G.gcp_adam_step(A, Gr, B, Cm, k + 1, lr=1e-3, lower=0.0, zero_grad=True)
+        if k == warmup - 1:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    t.status()
+    kms = [a.elapsed_time(b) for a, b in ev]
+    kmed = float(np.median(kms))
+    alg = algorithmic_bytes(3, R, P, Q)
+    return {"workload": f"Amazon-shaped count tensor {dims[0]}x{dims[1]}x{dims[2]}, {nnz} nonzeros, rank {R} "
+                        f"FP32, {P}+{Q} stratified samples per step (mixed-radix cell keys)",
+            "factor_bytes": A.numel() * 4, "tensor_handle_bytes": t.device_bytes(), "generation_s": gen_s,
+            "steps": steps, "samples_per_s": steps * (P + Q) / wall, "ms_per_step": 1e3 * wall / steps,
+            "loss_grad_ms_median": kmed, "algorithmic_bytes_per_launch": alg,
+            "algorithmic_gbs": alg / (kmed * 1e-3) / 1e9,
+            "frac": alg / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +351,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the GCP-FedAdam round and autograd measurements")
-    ap.add_argument("--fed-rounds", type=int, default=3)
+    ap.add_argument("--fed-rounds", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times, so that "
                          "rocprofv3's FETCH_SIZE / WRITE_SIZE can be calibrated against known bytes")
@@ -299,7 +361,14 @@ def main():
                     help="fixed sampled-gradient tile instead of the autotuned one, as comma-separated "
                          "key=value pairs of gcp_tile fields (e.g. lanes=8,vec=4,block=256,bucket_block=1024); "
                          "'default' = the library's automatic choice")
+    ap.add_argument("--hbm-resident", action="store_true",
+                    help="only run the HBM-resident-factor experiment (Amazon-shaped tensor) and print its JSON")
+    ap.add_argument("--hbm-nnz", type=int, default=500_000_000)
     args = ap.parse_args()
+    if args.hbm_resident:
+        out = hbm_resident(torch.device("cuda:0"), args.hbm_nnz, max(1, min(args.steps, 50)), args.warmup)
+        print(json.dumps(out))
+        return
     if args.fused_experiment:
         out = fused_experiment(torch.device("cuda:0"), [1 << k for k in (14, 16, 18, 20, 22)], 20)
         print(json.dumps(out))
@@ -335,8 +404,11 @@ def main():
     alg = algorithmic_bytes(3, RANK, P, Q)
     achieved = alg / (kmean * 1e-3) / 1e9
     traffic = measured_traffic()
+    traffic_gbs = traffic / (kmean * 1e-3) / 1e9 if traffic else None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_gbs": round(traffic_gbs, 1) if traffic_gbs else None,
+            "traffic_frac": round(traffic_gbs / HBM_PEAK_GBS, 4) if traffic_gbs else None,
             "kernel": "gcp_loss_grad: k_loss_grad (sampling, model values, loss derivative, scatter or "
                       "row-block sort) + k_bucket_accum (row-block owner pass) when bucketed",
             "kernel_ms_mean": round(kmean, 5), "kernel_ms_median": round(float(np.median(kms)), 5),
@@ -355,9 +427,9 @@ def main():
     if not args.no_extras:
         extras["fedadam"] = run_fedadam(dev, args.fed_rounds)
         torch.cuda.empty_cache()
-        extras["autograd_dense_gaussian"] = run_autograd(dev, "dense_gaussian", 10)
+        extras["autograd_dense_gaussian"] = run_autograd(dev, "dense_gaussian", 20)
         torch.cuda.empty_cache()
-        extras["autograd_binary_bernoulli"] = run_autograd(dev, "binary_bernoulli", 5)
+        extras["autograd_binary_bernoulli"] = run_autograd(dev, "binary_bernoulli", 20)
     out = {
         "metric": "sampled gradient entries/sec + HBM GB/s fraction; batched vs plain speedup",
         "value": value,

@@ -165,7 +165,8 @@ int64_t gcp_struct_size(const char* name);
 
 /* Sparse COO tensor (Sec. 3.1.1: N coordinate tuples and N values).
  * dims_host: d host int64 mode sizes (1 <= d <= 8, I_k >= 1, sum_k
- * ceil(log2 I_k) <= 63).  coords_dev: device int64 [nnz x d]; vals_dev:
+ * ceil(log2 I_k) <= 63 and sum_k I_k < 2^32 model rows, else
+ * GCP_ERR_UNSUPPORTED).  coords_dev: device int64 [nnz x d]; vals_dev:
  * device values of dtype dt.  Copies and packs the nonzeros into 16-byte
  * device records and builds an open-addressing hash table of the packed
  * coordinates (the O(1) membership search of Sec. 3.1.1).  The inputs may be
@@ -177,7 +178,7 @@ gcp_status gcp_tensor_create(gcp_tensor* out, int d, const int64_t* dims_host, i
                              hipStream_t stream);
 
 /* Dense tensor of prod_k I_k values, row-major (last mode fastest), for
- * UNIFORM sampling.  BORROWS vals_dev: the caller keeps it alive and
+ * UNIFORM sampling (dimension limits as for gcp_tensor_create).  BORROWS vals_dev: the caller keeps it alive and
  * unchanged while the handle is used. */
 gcp_status gcp_tensor_create_dense(gcp_tensor* out, int d, const int64_t* dims_host,
                                    const void* vals_dev, gcp_dtype dt, hipStream_t stream);

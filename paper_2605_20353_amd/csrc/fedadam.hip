@@ -391,7 +391,9 @@ static gcp_status fed_build(gcp_fed_s* f)
     if (D.batched) {
         gcp_status st = GCP_OK;
         FedKernel<T> kern = nullptr;
-        if (d == 3) kern = pick_fed<T, 3>(f->lanes, f->vec);
+        bool order3 = d == 3;
+        for (const gcp_fed_client& cl : f->clients) order3 = order3 && kernel_order(cl.tensor) == 3;
+        if (order3) kern = pick_fed<T, 3>(f->lanes, f->vec);
         else kern = pick_fed<T, 0>(f->lanes, f->vec);
         if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "batched lane shape lanes = %d, vec = %d not built", f->lanes,
                                     f->vec);
@@ -524,7 +526,7 @@ gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_
             return set_error(GCP_ERR_ARG, "client %d: tensor missing, dense, or of another dtype or order", c);
         }
         if (!cl.M || !cl.B || !cl.C || !cl.G) { delete f; return set_error(GCP_ERR_ARG, "client %d: NULL buffer", c); }
-        if (D.q > 0 && t->nnz >= t->cells) {
+        if (D.q > 0 && (uint64_t)t->nnz >= t->cells) {
             delete f;
             return set_error(GCP_ERR_ARG, "client %d: q > 0 but the block has no zero cells", c);
         }

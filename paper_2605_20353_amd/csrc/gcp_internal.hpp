@@ -3,7 +3,7 @@
 // Device-side building blocks of the sampled stochastic gradient:
 //   * Philox4x64-10 counter-based RNG and the exact [0, n) range map
 //     (the paper leaves the RNG open; counters make samples reproducible);
-//   * bit-packed coordinate keys and the open-addressing membership table
+//   * cell keys (bit-packed or mixed radix) and the open-addressing membership table
 //     (the O(1) hash search for zero samples, Sec. 3.1.1);
 //   * the three losses and their derivatives.
 #pragma once
@@ -36,15 +36,21 @@ enum : uint32_t {
 };
 
 constexpr int kMaxModes = 8;
-constexpr uint64_t kEmptySlot = ~0ull;      // never a packed key (keys use <= 63 bits)
+constexpr uint64_t kEmptySlot = ~0ull;      // never a cell key (see KeyLayout)
 
-// Bit-packed coordinates: mode k occupies bits [shift_k, shift_k + bits_k);
-// the last mode sits in the lowest bits.
+// One 64-bit key per cell.  Bit-packed when the modes' bit widths sum to at
+// most 63: mode k occupies bits [shift_k, shift_k + bits_k), the last mode the
+// lowest bits.  Otherwise mixed radix: the row-major linear index
+// sum_k i_k stride_k with stride_k = prod_{j > k} I_j, for any M < 2^64 - 1.
+// Neither form ever equals all ones, the empty hash slot.  Every I_k < 2^32.
 struct KeyLayout {
     int d;
+    int radix;                    // 0 bit-packed, 1 mixed radix
     int shift[kMaxModes];
     uint64_t mask[kMaxModes];
     int64_t dims[kMaxModes];
+    uint64_t stride[kMaxModes];   // mixed radix: prod_{j > k} I_j
+    double inv[kMaxModes];        // mixed radix: 1 / I_k, rounded to nearest
 };
 
 struct gcp_tensor_impl;
@@ -57,7 +63,7 @@ struct gcp_tensor_s {
     int64_t dims[gcp::kMaxModes] = {};
     int64_t rowoff[gcp::kMaxModes + 1] = {};  // first model row of each mode
     int64_t nnz = 0;
-    int64_t cells = 0;        // prod_k I_k
+    uint64_t cells = 0;       // prod_k I_k (< 2^64)
     gcp_dtype dt = GCP_F32;
     bool dense = false;
     gcp::KeyLayout layout{};
@@ -75,6 +81,15 @@ struct gcp_tensor_s {
     int64_t ws_bytes = 0;
     int64_t ws_max_samples = 0;        // samples per call the workspace was sized for
 };
+
+namespace gcp {
+// Order the kernels are specialised for: 3 and 4 have their own builds, every
+// other order -- and every mixed-radix key layout -- runs the general one (0).
+inline int kernel_order(const gcp_tensor_s* t)
+{
+    return (t->layout.radix || (t->d != 3 && t->d != 4)) ? 0 : t->d;
+}
+}  // namespace gcp
 
 namespace gcp {
 
@@ -143,14 +158,83 @@ __host__ __device__ __forceinline__ uint64_t range_map(uint64_t u, uint64_t n)
 
 enum : uint64_t { kStreamNonzero = 0, kStreamZero = 1, kStreamUniform = 2 };
 
-// --------------------------------------------------------- packed coords --
+// ------------------------------------------------------------- cell keys --
 
-__host__ __device__ __forceinline__ uint64_t unpack(const KeyLayout& L, uint64_t key, int k)
+// q = n / dv with r = n % dv, for n < 2^64 and 1 <= dv < 2^32 (inv = 1 / dv
+// rounded to nearest).  Each 32-bit digit of the quotient is estimated in
+// double precision, whose error stays below one unit, and corrected once
+// with exact integer arithmetic.
+__host__ __device__ __forceinline__ uint64_t divmod_u64_u32(uint64_t n, uint32_t dv, double inv, uint32_t& r)
 {
-    return (key >> L.shift[k]) & L.mask[k];
+    const uint32_t hi = (uint32_t)(n >> 32), lo = (uint32_t)n;
+    uint32_t qh = (uint32_t)((double)hi * inv);
+    int64_t rh = (int64_t)hi - (int64_t)qh * (int64_t)dv;
+    if (rh < 0) {
+        --qh;
+        rh += dv;
+    } else if (rh >= (int64_t)dv) {
+        ++qh;
+        rh -= dv;
+    }
+    const uint64_t x = ((uint64_t)rh << 32) | lo;     // < dv * 2^32: the low digit fits 32 bits
+    const double e = (double)x * inv;
+    uint32_t ql = e >= 4294967295.0 ? 0xffffffffu : (uint32_t)e;
+    int64_t rl = (int64_t)(x - (uint64_t)ql * dv);
+    if (rl < 0) {
+        --ql;
+        rl += dv;
+    } else if (rl >= (int64_t)dv) {
+        ++ql;
+        rl -= dv;
+    }
+    r = (uint32_t)rl;
+    return ((uint64_t)qh << 32) | ql;
 }
 
-// Candidate cell of sample s / attempt a drawn straight into a packed key.
+// Key term of coordinate c of mode k; a cell's key is the sum of its terms.
+// Code built with RADIX = false handles bit-packed layouts only (see unpack_all).
+template <bool RADIX = true>
+__host__ __device__ __forceinline__ uint64_t pack_coord(const KeyLayout& L, uint64_t c, int k)
+{
+    return (RADIX && L.radix) ? c * L.stride[k] : c << L.shift[k];
+}
+
+// All coordinates of a key (modes 0 .. dd-1 of at most DM).  Only code built
+// with RADIX = true reads mixed-radix keys: tensors whose layout is mixed
+// radix run the general-order kernels, so the order-specialised ones carry no
+// division code (and none of its registers).
+template <bool RADIX, int DM>
+__host__ __device__ __forceinline__ void unpack_all(const KeyLayout& L, int dd, uint64_t key, uint32_t (&c)[DM])
+{
+    if (!RADIX || !L.radix) {
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            c[k] = k < dd ? (uint32_t)((key >> L.shift[k]) & L.mask[k]) : 0u;
+    } else {
+#pragma unroll
+        for (int k = DM - 1; k >= 1; --k) {
+            c[k] = 0;
+            if (k < dd) key = divmod_u64_u32(key, (uint32_t)L.dims[k], L.inv[k], c[k]);
+        }
+        c[0] = (uint32_t)key;
+    }
+}
+
+// Coordinate of mode k (k may vary at run time) of a key.
+template <bool RADIX, int DM>
+__host__ __device__ __forceinline__ uint32_t unpack_one(const KeyLayout& L, int dd, uint64_t key, int k)
+{
+    if (!RADIX || !L.radix) return (uint32_t)((key >> L.shift[k]) & L.mask[k]);
+    uint32_t c[DM];
+    unpack_all<true>(L, dd, key, c);
+    uint32_t r = c[0];
+#pragma unroll
+    for (int j = 1; j < DM; ++j)
+        if (j == k) r = c[j];
+    return r;
+}
+
+// Candidate cell of sample s / attempt a drawn straight into a cell key.
 template <int D>
 __device__ __forceinline__ uint64_t draw_cell_key(const KeyLayout& L, int d, uint64_t seed, uint64_t client,
                                                   uint64_t s, uint64_t step, uint64_t stream, uint64_t attempt)
@@ -160,18 +244,18 @@ __device__ __forceinline__ uint64_t draw_cell_key(const KeyLayout& L, int d, uin
     U64x4 o = philox4x64_10(s, step, stream | (attempt << 8), 0, seed, client);
 #pragma unroll
     for (int k = 0; k < (D > 0 ? (D < 4 ? D : 4) : 4); ++k)
-        if (k < dd) key |= range_map(o.v[k], (uint64_t)L.dims[k]) << L.shift[k];
+        if (k < dd) key += pack_coord<D == 0>(L, range_map(o.v[k], (uint64_t)L.dims[k]), k);
     if (dd > 4) {
         U64x4 o2 = philox4x64_10(s, step, stream | (attempt << 8), 1, seed, client);
 #pragma unroll
         for (int k = 4; k < kMaxModes; ++k)
-            if (k < dd) key |= range_map(o2.v[k - 4], (uint64_t)L.dims[k]) << L.shift[k];
+            if (k < dd) key += pack_coord<D == 0>(L, range_map(o2.v[k - 4], (uint64_t)L.dims[k]), k);
     }
     return key;
 }
 
 // ------------------------------------------------------ membership table --
-// Open addressing with linear probing over 2^b slots holding packed keys;
+// Open addressing with linear probing over 2^b slots holding cell keys;
 // the home slot is the top b bits of a 64-bit finalising mix of the key
 // (the murmur3 fmix64 finaliser).
 

@@ -111,6 +111,13 @@ __device__ __forceinline__ void lds_add(double* p, double v)
     }
 }
 
+// Element offset of column 0 of model row `row` (row < 2^32, checked when the
+// tensor is created): one 32 x 32 -> 64-bit multiply.
+__device__ __forceinline__ uint64_t row_elem(uint64_t row, int R)
+{
+    return (uint64_t)(uint32_t)row * (uint32_t)R;
+}
+
 template <typename T>
 __device__ __forceinline__ uint4 pack_entry(uint64_t key, T y)
 {
@@ -217,7 +224,7 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                     if (k < dd) {
                         int64_t c = P.m_coords[s * dd + k];
                         if (c < 0 || c >= P.sc.L.dims[k]) ok = false;
-                        else key |= (uint64_t)c << P.sc.L.shift[k];
+                        else key += pack_coord<D == 0>(P.sc.L, (uint64_t)c, k);
                     }
                 }
                 x = P.m_x[s];
@@ -243,12 +250,14 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
             const int slot = (it + u) * S + g;
             const bool valid = s0 + slot < P.n;
             key[u] = skey[slot];
+            uint32_t ci[DM];
+            unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
 #pragma unroll
             for (int k = 0; k < DM; ++k) {
                 if (k < dd) {
-                    const int64_t row = P.rowoff[k] + (int64_t)unpack(P.sc.L, key[u], k);
+                    const uint64_t row = (uint64_t)P.rowoff[k] + ci[k];
                     if (col_ok && valid) {
-                        load_cols<T, VEC>(P.A + row * R + col0, a[u][k]);
+                        load_cols<T, VEC>(P.A + row_elem(row, R) + col0, a[u][k]);
                     } else {
 #pragma unroll
                         for (int v = 0; v < VEC; ++v) a[u][k][v] = T(0);
@@ -296,6 +305,10 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                 by[s - block_s0] = y;
             }
             if (!col_ok) continue;
+            // coordinates again from the key (a few shifts when bit-packed),
+            // rather than holding them live across the gathers
+            uint32_t ci[DM];
+            unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
                 // leave-one-out products by prefix and suffix running products
@@ -311,11 +324,11 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                         const T c = pre[k] * suf;
                         suf *= a[u][k][v];
                         if ((P.bucket_mask >> k) & 1u) continue;
-                        const int64_t i = (int64_t)unpack(P.sc.L, key[u], k);
+                        const uint32_t i = ci[k];
                         if ((P.lds_mask >> k) & 1u) {
-                            lds_add(priv + P.lds_off[k] + i * R + col0 + v, c);
+                            lds_add(priv + P.lds_off[k] + i * (uint32_t)R + col0 + v, c);
                         } else {
-                            global_add(P.G + (P.rowoff[k] + i) * R + col0 + v, c);
+                            global_add(P.G + row_elem((uint64_t)P.rowoff[k] + i, R) + col0 + v, c);
                         }
                     }
                 }

@@ -6,7 +6,7 @@
 // at a time):
 //   phase 1, one lane per sample: draw the sample (Philox, nonzero record
 //     read or zero-candidate hash probes) or read it from a materialised
-//     list, and stage (packed key, x, w) in the wave's LDS slice;
+//     list, and stage (cell key, x, w) in the wave's LDS slice;
 //   phase 2, LANES lanes per sample with VEC consecutive columns each, 64 /
 //     LANES samples per pass and U samples per lane group in flight: gather
 //     the d factor rows, m = sum_r prod_k A_k[i_k, r] (eq. cp) by a butterfly
@@ -104,14 +104,13 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
         const int nvalid = (int)std::min<int64_t>(P.spb, P.n - block_s0);
         for (int b = threadIdx.x; b < P.nb; b += blockDim.x) bcnt[b] = 0;
         __syncthreads();
+        for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
+            uint32_t ci[DM];
+            unpack_all<D == 0>(P.sc.L, dd, bkey[e], ci);
 #pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            if (k < dd && ((P.bucket_mask >> k) & 1u)) {
-                for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
-                    const int b = P.bucket_base[k] + (int)(unpack(P.sc.L, bkey[e], k) >> P.br_shift);
-                    atomicAdd(bcnt + b, 1);
-                }
-            }
+            for (int k = 0; k < DM; ++k)
+                if (k < dd && ((P.bucket_mask >> k) & 1u))
+                    atomicAdd(bcnt + P.bucket_base[k] + (int)(ci[k] >> P.br_shift), 1);
         }
         __syncthreads();
         if (wave == 0) wave_exclusive_scan(bcnt, boff, P.nb, lane);
@@ -122,14 +121,16 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
         }
         __syncthreads();
         uint4* seg = P.entries + (int64_t)blockIdx.x * P.entry_cap;
+        for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
+            const uint64_t key = bkey[e];
+            const uint4 ent = pack_entry<T>(key, by[e]);
+            uint32_t ci[DM];
+            unpack_all<D == 0>(P.sc.L, dd, key, ci);
 #pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            if (k < dd && ((P.bucket_mask >> k) & 1u)) {
-                for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
-                    const uint64_t key = bkey[e];
-                    const int b = P.bucket_base[k] + (int)(unpack(P.sc.L, key, k) >> P.br_shift);
-                    const int pos = atomicAdd(boff + b, 1);
-                    seg[pos] = pack_entry<T>(key, by[e]);
+            for (int k = 0; k < DM; ++k) {
+                if (k < dd && ((P.bucket_mask >> k) & 1u)) {
+                    const int pos = atomicAdd(boff + P.bucket_base[k] + (int)(ci[k] >> P.br_shift), 1);
+                    seg[pos] = ent;
                 }
             }
         }
@@ -206,13 +207,15 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
                 const int en = e + S * U;
                 nxt[u] = en < cnt ? seg[en] : make_uint4(0, 0, 0, 0);
                 key[u] = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
+                uint32_t ci[DM];
+                unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
                 y[u] = valid ? entry_y<T>(ent) : T(0);
 #pragma unroll
                 for (int kk = 0; kk < DM; ++kk) {
                     if (kk < dd) {
                         if (kk != k && col_ok && valid) {
-                            const int64_t row = P.rowoff[kk] + (int64_t)unpack(P.sc.L, key[u], kk);
-                            load_cols<T, VEC>(P.A + row * R + col0, a[u][kk]);
+                            const uint64_t row = (uint64_t)P.rowoff[kk] + ci[kk];
+                            load_cols<T, VEC>(P.A + row_elem(row, R) + col0, a[u][kk]);
                         } else {
 #pragma unroll
                             for (int v = 0; v < VEC; ++v) a[u][kk][v] = T(1);
@@ -224,7 +227,7 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
             for (int u = 0; u < U; ++u) {
                 const int e = base + u * S + g;
                 if (e >= cnt || !col_ok) continue;
-                const int64_t i = (int64_t)unpack(P.sc.L, key[u], k) - r0;
+                const uint32_t i = unpack_one<D == 0, DM>(P.sc.L, dd, key[u], k) - (uint32_t)r0;
                 T c[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
                     for (int kk = 0; kk < DM; ++kk)
                         if (kk < dd) c[v] *= a[u][kk][v];
                 }
-                T* dst = part + i * R + col0;
+                T* dst = part + i * (uint32_t)R + col0;
                 lds_add(dst, c[0]);
                 if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
                 if constexpr (VEC > 2) {
@@ -423,9 +426,21 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
         const int budget = (tile && tile->bucket_lds_bytes > 0) ? tile->bucket_lds_bytes : kBucketLdsBudget;
         if (budget < 8192) return set_error(GCP_ERR_ARG, "bucket_lds_bytes = %d < 8192", budget);
         while (((int64_t)2 << br_shift) * R * (int64_t)sizeof(T) <= budget && br_shift < 30) ++br_shift;
+        int64_t nb_all = 0;
+        for (int k = 0; k < d; ++k)
+            if ((bucket_mask >> k) & 1u) nb_all += ceil_div(t->dims[k], int64_t(1) << br_shift);
+        // automatic choice: modes with more row blocks than the owner pass
+        // indexes (tall factor matrices, under one sample per row) keep the
+        // atomic scatter
+        if (req_bucket < 0 && nb_all > kMaxBuckets) bucket_mask = 0;
+    }
+    if (bucket_mask) {
+        const int budget = (tile && tile->bucket_lds_bytes > 0) ? tile->bucket_lds_bytes : kBucketLdsBudget;
         for (int k = 0; k < d; ++k) {
             P.bucket_base[k] = nb;
             if ((bucket_mask >> k) & 1u) {
+                if (nb + ceil_div(t->dims[k], int64_t(1) << br_shift) > kMaxBuckets)
+                    return set_error(GCP_ERR_UNSUPPORTED, "more than %d row blocks of %d bytes", kMaxBuckets, budget);
                 nb += (int)ceil_div(t->dims[k], int64_t(1) << br_shift);
                 ++nbm;
             }
@@ -441,7 +456,6 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
         }
         if (spb % 64 != 0 || spb < 512 || spb > 8192) return set_error(GCP_ERR_ARG, "bucket_block_samples = %d", spb);
         nblocks = ceil_div(n, spb);
-        if (nb > kMaxBuckets) return set_error(GCP_ERR_UNSUPPORTED, "%d row blocks exceed %d", nb, kMaxBuckets);
         if (!t->ws) return set_error(GCP_ERR_ARG, "bucketed scatter needs gcp_tensor_reserve first");
         if (n > t->ws_max_samples || nblocks * spb * (int64_t)nbm > t->ws_entries || (int64_t)nb * nblocks > t->ws_hist)
             return set_error(GCP_ERR_ARG, "workspace reserved by gcp_tensor_reserve is too small for this call");
@@ -466,11 +480,11 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (R % vec != 0) return set_error(GCP_ERR_ARG, "vec = %d does not divide R = %d", vec, R);
     if (lanes * vec < R) return set_error(GCP_ERR_ARG, "lanes*vec = %d < R = %d", lanes * vec, R);
     const int src = smp ? 1 : 0;
-    if (sizeof(T) == 8 && t->d != 3 && t->d != 4 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
+    if (sizeof(T) == 8 && kernel_order(t) == 0 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
         lanes = 32;
         vec = 2;
     }
-    LGKernel<T> kern = pick_kernel<T>(t->d, src, lanes, vec);
+    LGKernel<T> kern = pick_kernel<T>(kernel_order(t), src, lanes, vec);
     if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "tile lanes = %d, vec = %d not built for this dtype", lanes, vec);
     const uintptr_t align = (uintptr_t)vec * sizeof(T);
     if (((uintptr_t)A % align) != 0) return set_error(GCP_ERR_ARG, "A is not %d-byte aligned", (int)align);
@@ -549,7 +563,7 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds_bytes, stream, P);
     GCP_HIP(hipGetLastError());
     if (bucket_mask) {
-        BAKernel<T> bk = pick_bucket_kernel<T>(d, lanes, vec);
+        BAKernel<T> bk = pick_bucket_kernel<T>(kernel_order(t), lanes, vec);
         if (!bk) return set_error(GCP_ERR_UNSUPPORTED, "no bucket kernel for lanes = %d, vec = %d", lanes, vec);
         const int bblock = (tile && tile->bucket_block > 0) ? tile->bucket_block : 1024;
         if (bblock % 64 != 0 || bblock > 1024) return set_error(GCP_ERR_ARG, "bucket_block = %d", bblock);

@@ -15,9 +15,12 @@ __global__ void __launch_bounds__(256) k_sample(SampleCtx<T> c, int64_t n, int64
         uint64_t key;
         T x, w;
         draw_sample<T, D>(c, c.step, s, key, x, w);
+        constexpr int DM = D > 0 ? D : kMaxModes;
+        uint32_t ci[DM];
+        unpack_all<D == 0>(c.L, dd, key, ci);
 #pragma unroll
-        for (int k = 0; k < kMaxModes; ++k)
-            if (k < dd) coords[s * dd + k] = (int64_t)unpack(c.L, key, k);
+        for (int k = 0; k < DM; ++k)
+            if (k < dd) coords[s * dd + k] = (int64_t)ci[k];
         xo[s] = x;
         wo[s] = w;
     }
@@ -34,9 +37,10 @@ static gcp_status launch_sample(const gcp_tensor_s* t, const gcp_sample_params* 
     if (n == 0) return GCP_OK;
     if (!coords || !x || !w) return set_error(GCP_ERR_ARG, "output pointer is NULL");
     int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)device_cu_count(t->device) * 16);
-    if (t->d == 3)
+    const int order = kernel_order(t);
+    if (order == 3)
         k_sample<T, 3><<<(unsigned)blocks, 256, 0, stream>>>(c, n, coords, (T*)x, (T*)w);
-    else if (t->d == 4)
+    else if (order == 4)
         k_sample<T, 4><<<(unsigned)blocks, 256, 0, stream>>>(c, n, coords, (T*)x, (T*)w);
     else
         k_sample<T, 0><<<(unsigned)blocks, 256, 0, stream>>>(c, n, coords, (T*)x, (T*)w);

@@ -43,7 +43,7 @@ struct SampleCtx {
     uint32_t* status;
 };
 
-// Fills the packed key, value and weight of sample s in [0, p + q) of
+// Fills the cell key, value and weight of sample s in [0, p + q) of
 // iteration `step` (the second Philox counter word).
 template <typename T, int D>
 __device__ __forceinline__ void draw_sample(const SampleCtx<T>& c, uint64_t step, int64_t s, uint64_t& key, T& x,
@@ -53,9 +53,12 @@ __device__ __forceinline__ void draw_sample(const SampleCtx<T>& c, uint64_t step
         key = draw_cell_key<D>(c.L, c.d, c.seed, c.client, (uint64_t)s, step, kStreamUniform, 0);
         int64_t lin = 0;
         const int dd = D > 0 ? D : c.d;
+        constexpr int DM = D > 0 ? D : kMaxModes;
+        uint32_t ci[DM];
+        unpack_all<D == 0>(c.L, dd, key, ci);
 #pragma unroll
-        for (int k = 0; k < kMaxModes; ++k)
-            if (k < dd) lin += (int64_t)unpack(c.L, key, k) * c.dense_stride[k];
+        for (int k = 0; k < DM; ++k)
+            if (k < dd) lin += (int64_t)ci[k] * c.dense_stride[k];
         x = c.dense[lin];
         w = c.w_nz;
         return;
@@ -115,7 +118,7 @@ inline gcp_status make_sample_ctx(const gcp_tensor_s* t, const gcp_sample_params
     case GCP_SAMPLE_STRATIFIED:
     case GCP_SAMPLE_SEMI_STRATIFIED:
         if (t->dense) return set_error(GCP_ERR_UNSUPPORTED, "stratified sampling needs a sparse tensor");
-        if (sp->kind == GCP_SAMPLE_STRATIFIED && sp->q > 0 && t->nnz >= t->cells)
+        if (sp->kind == GCP_SAMPLE_STRATIFIED && sp->q > 0 && (uint64_t)t->nnz >= t->cells)
             return set_error(GCP_ERR_ARG, "q > 0 but the tensor has no zero cells");
         c.w_nz = sp->p > 0 ? T((double)t->nnz / (double)sp->p) : T(0);
         c.w_z = sp->q > 0 ? T((double)(t->cells - t->nnz) / (double)sp->q) : T(0);

@@ -75,7 +75,7 @@ static int bits_for(int64_t n)
     return b;
 }
 
-// Shared by sparse and dense handles: dims, row offsets, packed-key layout.
+// Shared by sparse and dense handles: dims, row offsets, cell-key layout.
 static gcp_status init_shape(gcp_tensor_s* t, int d, const int64_t* dims)
 {
     if (d < 1 || d > kMaxModes) return set_error(GCP_ERR_ARG, "d = %d outside [1, %d]", d, kMaxModes);
@@ -83,26 +83,38 @@ static gcp_status init_shape(gcp_tensor_s* t, int d, const int64_t* dims)
     t->d = d;
     t->layout.d = d;
     int total_bits = 0;
-    int64_t cells = 1;
+    uint64_t cells = 1;
     bool overflow = false;
     t->rowoff[0] = 0;
     for (int k = 0; k < d; ++k) {
         if (dims[k] < 1) return set_error(GCP_ERR_ARG, "dims[%d] = %lld < 1", k, (long long)dims[k]);
+        if (dims[k] >= (int64_t(1) << 32))
+            return set_error(GCP_ERR_UNSUPPORTED, "dims[%d] = %lld needs more than 32-bit indices", k,
+                             (long long)dims[k]);
         t->dims[k] = dims[k];
         t->layout.dims[k] = dims[k];
         t->rowoff[k + 1] = t->rowoff[k] + dims[k];
-        if (__builtin_mul_overflow(cells, dims[k], &cells)) overflow = true;
+        if (__builtin_mul_overflow(cells, (uint64_t)dims[k], &cells)) overflow = true;
     }
+    if (t->rowoff[d] >= (int64_t(1) << 32))
+        return set_error(GCP_ERR_UNSUPPORTED, "sum of the dimensions %lld needs more than 32-bit model rows",
+                         (long long)t->rowoff[d]);
+    if (overflow || cells == ~0ull)
+        return set_error(GCP_ERR_UNSUPPORTED, "the cell count prod_k I_k is not below 2^64 - 1");
     for (int k = d - 1; k >= 0; --k) {
         int b = bits_for(dims[k]);
         t->layout.shift[k] = total_bits;
-        t->layout.mask[k] = b == 0 ? 0 : ((b >= 64) ? ~0ull : ((1ull << b) - 1));
+        t->layout.mask[k] = b == 0 ? 0 : ((1ull << b) - 1);
         total_bits += b;
     }
-    if (total_bits > 63 || overflow)
-        return set_error(GCP_ERR_UNSUPPORTED,
-                         "packed coordinates need %d bits (> 63) or the cell count overflows int64",
-                         total_bits);
+    // bit-packed keys when they fit 63 bits, else the mixed-radix linear index
+    t->layout.radix = total_bits > 63 ? 1 : 0;
+    uint64_t stride = 1;
+    for (int k = d - 1; k >= 0; --k) {
+        t->layout.stride[k] = stride;
+        t->layout.inv[k] = 1.0 / (double)dims[k];
+        stride *= (uint64_t)dims[k];
+    }
     t->cells = cells;
     return GCP_OK;
 }
@@ -121,7 +133,7 @@ __global__ void k_build(KeyLayout L, int64_t nnz, const int64_t* __restrict__ co
     for (int k = 0; k < L.d; ++k) {
         int64_t c = coords[j * L.d + k];
         if (c < 0 || c >= L.dims[k]) ok = false;
-        else key |= (uint64_t)c << L.shift[k];
+        else key += pack_coord(L, (uint64_t)c, k);
     }
     Record<T> r;
     r.key = ok ? key : 0;
@@ -185,7 +197,7 @@ gcp_status gcp_tensor_create(gcp_tensor* out, int d, const int64_t* dims_host, i
     if (!t) return set_error(GCP_ERR_OOM, "host allocation");
     gcp_status st = init_shape(t, d, dims_host);
     if (st != GCP_OK) { delete t; return st; }
-    if (nnz < 1 || nnz > t->cells) {
+    if (nnz < 1 || (uint64_t)nnz > t->cells) {
         delete t;
         return set_error(GCP_ERR_ARG, "nnz = %lld outside [1, prod dims]", (long long)nnz);
     }
@@ -246,9 +258,13 @@ gcp_status gcp_tensor_create_dense(gcp_tensor* out, int d, const int64_t* dims_h
     if (!t) return set_error(GCP_ERR_OOM, "host allocation");
     gcp_status st = init_shape(t, d, dims_host);
     if (st != GCP_OK) { delete t; return st; }
+    if (t->cells >= (uint64_t(1) << 48)) {
+        delete t;
+        return set_error(GCP_ERR_ARG, "a dense tensor of %llu cells", (unsigned long long)t->cells);
+    }
     t->dense = true;
     t->dt = dt;
-    t->nnz = t->cells;
+    t->nnz = (int64_t)t->cells;
     t->dense_vals = vals_dev;
     (void)hipGetDevice(&t->device);
     hipError_t e;

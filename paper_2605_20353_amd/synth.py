@@ -86,20 +86,33 @@ def events_to_tensor(dims, factors, lam, nnz: int, seed: int, device="cpu",
         cdf = cdf + torch.arange(R, device=device, dtype=torch.float64)[:, None]
         flat_cdf.append(cdf.reshape(-1).contiguous())
     st = strides(dims)
+    # Above 2^63 cells the int64 linear key wraps; the wrapped bit pattern is
+    # still one-to-one with the cell (the count is below 2^64), so duplicates
+    # are still found on it, and the coordinates are kept per event instead of
+    # being divided back out of the key.
+    wide = total >= (1 << 63)
     if batch is None:
-        batch = max(1 << 12, min(1 << 25, nnz // 4 + 1))
-    keys = []
+        batch = max(1 << 12, min(max(1 << 25, nnz // 8), nnz // 4 + 1))
+    keys, ev_coords = [], []
     n_events = 0
     for _ in range(max_batches):
         r = torch.multinomial(probs, batch, replacement=True, generator=g)
         key = torch.zeros(batch, dtype=torch.int64, device=device)
+        if wide:
+            cs = torch.empty(batch, d, dtype=torch.int32, device=device)
         for k in range(d):
             u = torch.rand(batch, dtype=torch.float64, device=device, generator=g)
             pos = torch.searchsorted(flat_cdf[k], r.to(torch.float64) + u)
             i = pos - r * int(dims[k])
             i = i.clamp_(0, int(dims[k]) - 1)
-            key += i * st[k]
+            if wide:
+                cs[:, k] = i.to(torch.int32)
+                key += i * (st[k] if st[k] < (1 << 63) else st[k] - (1 << 64))   # modulo 2^64
+            else:
+                key += i * st[k]
         keys.append(key)
+        if wide:
+            ev_coords.append(cs)
         n_events += batch
         distinct = torch.unique(torch.cat(keys)).numel()
         if distinct >= nnz:
@@ -107,13 +120,17 @@ def events_to_tensor(dims, factors, lam, nnz: int, seed: int, device="cpu",
     else:
         raise RuntimeError("event sampling did not reach the nonzero target")
     allk = torch.cat(keys)
+    del keys
     uniq, inv, counts = torch.unique(allk, sorted=True, return_inverse=True, return_counts=True)
     pos = torch.arange(allk.numel(), device=device)
     first = torch.full((uniq.numel(),), allk.numel(), dtype=torch.int64, device=device)
     first.scatter_reduce_(0, inv, pos, reduce="amin")
     order = torch.argsort(first)[:nnz]
-    keep = uniq[order]
     vals = counts[order].to(torch.float64)
+    if wide:
+        coords = torch.cat(ev_coords)[first[order]].to(torch.int64)
+        return coords, vals
+    keep = uniq[order]
     coords = torch.empty(nnz, d, dtype=torch.int64, device=device)
     rem = keep.clone()
     for k in range(d):

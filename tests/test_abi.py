@@ -46,6 +46,22 @@ def test_host_argument_errors_without_gpu():
     assert L.gcp_adam_step(None, None, None, None, 0, 0, 1, 1e-3, .9, .999, 1e-8, 0.0, 0, None) == _lib.GCP_OK
 
 
+def test_cell_key_limits_without_gpu():
+    # a mode of 2^32 indices, a sum of dimensions of 2^32 model rows or more,
+    # or 2^64 - 1 cells or more: unsupported, decided before any device work
+    L = _lib.lib()
+    h = C.c_void_p()
+    for dims in ((1 << 32, 2, 2), (3_000_000_000, 1_500_000_000, 1), (4_000_000, 4_000_000, 4_000_000)):
+        arr = (C.c_int64 * 3)(*dims)
+        assert L.gcp_tensor_create(C.byref(h), 3, arr, 5, None, None, 0, None) == _lib.GCP_ERR_UNSUPPORTED, dims
+    # 23 + 21 + 21 coordinate bits (more than a bit-packed key holds) but
+    # under 2^64 cells: the shape is accepted and the NULL coordinates are
+    # what the call rejects
+    amazon = (C.c_int64 * 3)(4821207, 1774269, 1805187)
+    assert L.gcp_tensor_create(C.byref(h), 3, amazon, 5, None, None, 0, None) == _lib.GCP_ERR_ARG
+    assert b"coords" in L.gcp_last_error() or b"NULL" in L.gcp_last_error()
+
+
 def test_struct_layouts_match_the_binding():
     import ctypes as C
     from paper_2605_20353_amd import fedadam

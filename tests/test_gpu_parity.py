@@ -130,6 +130,73 @@ def test_semi_stratified_samples_bit_exact(gpu, dtype):
     np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
 
 
+# ------------------------------------------------- mixed-radix cell keys --
+
+# coordinate bit widths summing past 63: the library keys cells by their
+# row-major linear index instead of bit-packing them
+RADIX_CASES = {
+    "amazon_65bit": [4821207, 1774269, 1805187],     # 23 + 21 + 21 bits, M ~ 1.54e19 > 2^63
+    "4way_64bit": [40000, 40000, 40000, 40000],      # 4 x 16 bits, M = 2.56e18
+}
+
+
+def radix_case(name, dtype, gpu, q, seed, step):
+    """~20000 event-sampled nonzeros plus, planted as nonzeros, the first zero
+    candidate of every other zero sample of (seed, step), so that those zero
+    samples are decided by the membership test and redrawn."""
+    dims = RADIX_CASES[name]
+    d = len(dims)
+    data = synth.count_tensor(dims, 3, 20000, seed=2613)
+    planted = []
+    for s in range(0, q, 2):
+        o = oracle.philox4x64_10([s, step, 1, 0], [seed, 0])
+        planted.append([oracle.range_map(int(o[k]), dims[k]) for k in range(d)])
+    coords = np.concatenate([data.coords.numpy(), np.array(planted, dtype=np.int64)])
+    vals = np.concatenate([data.vals.numpy(), np.ones(len(planted))])
+    coords, first = np.unique(coords, axis=0, return_index=True)
+    vals = vals[first]
+    t_gpu = G.SparseTensor(dims, torch.from_numpy(coords).to(gpu), torch.from_numpy(vals).to(dtype).to(gpu))
+    t_ora = oracle.SparseTensor(dims, coords, torch.from_numpy(vals).to(dtype).double().numpy())
+    return t_gpu, t_ora, dims, planted
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", list(RADIX_CASES))
+def test_mixed_radix_keys_match_oracle(gpu, dtype, name):
+    """Bit-exact samples (stratified and semi-stratified) and gradients of the
+    fused, materialised, atomic and (4-way) row-bucketed paths on tensors whose
+    cells need the mixed-radix key."""
+    q, seed, step, R = 2000, 13, 4, 4
+    t_gpu, t_ora, dims, planted = radix_case(name, dtype, gpu, q, seed, step)
+    say(f"mixed radix {name} {dtype}: {t_ora.nnz} nonzeros")
+    A = model(dims, R, dtype, gpu)
+    for kind in ("stratified", "semi_stratified"):
+        sp = G.SampleParams(kind, 3000, q, seed=seed, step=step)
+        c, x, w = G.gcp_sample(t_gpu, sp)
+        t_gpu.status()
+        oc, ox, ow = oracle.sample_stratified(t_ora, sp.p, q, seed, step, semi=(kind == "semi_stratified"))
+        np.testing.assert_array_equal(c.cpu().numpy(), oc)
+        np.testing.assert_array_equal(x.cpu().numpy(), ox.astype(x.cpu().numpy().dtype))
+        np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
+        zc = oc[sp.p:]
+        if kind == "stratified":      # the planted candidates were rejected and redrawn
+            assert all(list(zc[s]) != planted[s // 2] for s in range(0, q, 2))
+        else:                         # semi-stratified keeps the first candidate
+            assert all(list(zc[s]) == planted[s // 2] for s in range(0, q, 2))
+        Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+        tiles = [G.Tile(), G.Tile(lds_modes=0, bucket_modes=0)]
+        if name == "4way_64bit":
+            t_gpu.reserve(sp.n, R)
+            tiles.append(G.Tile(lds_modes=0, bucket_modes=15))
+        for tile in tiles:
+            Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=tile)
+            t_gpu.status()
+            assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype], (kind, tile)
+            assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+        Gm, _ = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", samples=(c, x, w))
+        assert split_rel_err(Gm.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+
+
 # --------------------------------------------------------------- gradient --
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
