@@ -143,7 +143,7 @@ def loss_grad_candidates(R: int, dtype, reserved: bool):
                     shapes.append((vec, lanes))
         for vec, lanes in shapes:
             for block in (256, 512):
-                for bblock, splits in ((1024, 0), (512, 0), (512, 32), (1024, 32)):
+                for bblock, splits in ((1024, 0), (1024, 16), (1024, 32), (512, 0), (512, 32)):
                     out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=-1, bucket_modes=-1,
                                       bucket_splits=splits, bucket_block=bblock))
     return out
