@@ -201,7 +201,8 @@ def run_fedadam(dev, rounds: int):
     fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True)
     tile = autotune.tune_fedadam(fed, rounds=1, warmup=1, use_cache=False)
     out["batched_tile"] = {"workgroups_per_client": tile.workgroups_per_client, "block": tile.block,
-                           "lanes": tile.lanes, "vec": tile.vec}
+                           "lanes": tile.lanes, "vec": tile.vec, "lds_modes": tile.lds_modes,
+                           "bucket_modes": tile.bucket_modes}
     out["batched_ms_per_round"] = _median_ms(lambda: fed.round(0), rounds, 1)
     fed.status()
     fed.close()

@@ -282,6 +282,17 @@ typedef struct gcp_fed_desc {
                                  is accumulated in each workgroup's LDS and
                                  flushed once per local step; -1 = automatic
                                  (modes whose largest client block fits), 0 = none */
+    int32_t bucket_modes;     /* batched: bitmask of modes scattered by the row-
+                                 bucketed (sort-by-row) scheme inside the launch:
+                                 each client's workgroups sort their samples by
+                                 row block, then each owns whole row blocks and
+                                 writes them without atomics (modes that are
+                                 LDS-private are left out); 0 or -1 = none, the
+                                 hardware-atomic scatter, which measured faster
+                                 in the persistent launch (its LDS leaves one
+                                 workgroup per CU)                              */
+    int32_t bucket_block_samples; /* samples per sorted block, multiple of 64 in
+                                 [512, 8192]; 0 = 2048                            */
     int64_t p;                /* nonzero samples per client and local step       */
     int64_t q;                /* zero samples per client and local step          */
     uint64_t seed;

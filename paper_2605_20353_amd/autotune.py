@@ -61,8 +61,11 @@ def _time(fn, stream, reps: int, warmup: int) -> float:
 
 # ------------------------------------------------------------ FedAdam round --
 
-def fed_candidates(R: int, dtype, nclients: int, cus: int = 256):
-    """Launch shapes worth trying for a batched round."""
+def fed_candidates(R: int, dtype, nclients: int, cus: int = 256, nmodes: int = 3):
+    """Launch shapes worth trying for a batched round: atomic scatter over
+    lane shapes, workgroup sizes and workgroups per client, then the
+    row-bucketed scatter (whose LDS keeps about one workgroup per CU) over
+    lane shapes and workgroup sizes."""
     shapes = [(32, 1), (16, 2)] if R == 32 else [(0, 0)]
     if dtype == torch.float32 and R == 32:
         shapes.append((8, 4))
@@ -73,7 +76,11 @@ def fed_candidates(R: int, dtype, nclients: int, cus: int = 256):
             if w > max_w:
                 continue
             for lanes, vec in shapes:
-                out.append(FedTile(workgroups_per_client=w, block=block, lanes=lanes, vec=vec))
+                out.append(FedTile(workgroups_per_client=w, block=block, lanes=lanes, vec=vec, bucket_modes=0))
+    all_modes = (1 << nmodes) - 1
+    for block in (512, 1024):
+        for lanes, vec in shapes:
+            out.append(FedTile(workgroups_per_client=0, block=block, lanes=lanes, vec=vec, bucket_modes=all_modes))
     return out
 
 
@@ -95,7 +102,7 @@ def tune_fedadam(fed: FedAdam, candidates=None, rounds: int = 1, warmup: int = 1
         tile = FedTile(**cache[key]["tile"])
         fed.retile(tile)
         return tile
-    cands = candidates or fed_candidates(fed.cfg.R, fed.dtype, len(fed.clients))
+    cands = candidates or fed_candidates(fed.cfg.R, fed.dtype, len(fed.clients), nmodes=len(fed.global_dims))
     snap = fed.snapshot()
     results = []
     for tile in cands:

@@ -5,8 +5,11 @@
 // Persistent launch: client c owns W consecutive workgroups.  Per round they
 // copy the client's rows of the server model into M_c, then for each of the
 // tau local steps: the sampled gradient of the client's block (the same
-// per-chunk body as gcp_loss_grad, hardware atomics into G_c), a group
-// barrier, Adam on M_c (which also re-zeroes G_c), a group barrier.  The
+// per-chunk body as gcp_loss_grad; small modes accumulate in LDS, large ones
+// either with hardware atomics into G_c or row-bucketed: the workgroups sort
+// their samples by row block, and after a group barrier each owns whole row
+// blocks, accumulates them in LDS and stores them into G_c), a group barrier,
+// Adam on M_c (which also re-zeroes G_c), a group barrier.  The
 // barrier is a per-client arrival counter in global memory with bounded
 // spinning: all K*W workgroups must be resident (checked at create), and a
 // barrier that waits too long records an error instead of hanging.
@@ -24,6 +27,7 @@ namespace gcp {
 constexpr uint32_t kStatusBarrier = 4u;
 constexpr long kSpinLimit = 1L << 22;
 constexpr int kFedLdsBudget = 64 * 1024;   // bytes of private client gradient per workgroup
+constexpr int kFedBucketRowBytes = 32 * 1024;   // LDS of one row block in the bucketed scatter
 
 template <typename T>
 struct FedClientDev {
@@ -120,9 +124,26 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
             for (int64_t e = threadIdx.x; e < P.lds_elems; e += blockDim.x) priv[e] = T(0);
             __syncthreads();
         }
-        for (int64_t chunk = (int64_t)w * nwaves + wave; chunk < P.nchunks; chunk += (int64_t)F.W * nwaves)
-            lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, nullptr, nullptr, 0, false, T(1),
-                                          lacc, step);
+        if (P.bucket_mask) {
+            // blocks of spb samples, each sorted by row block into this
+            // client's segment list of the same index
+            uint64_t* bkey = reinterpret_cast<uint64_t*>(smem + P.bucket_lds);
+            T* by = reinterpret_cast<T*>(smem + P.bucket_lds + (size_t)P.spb * 8);
+            int* bcnt = reinterpret_cast<int*>(smem + P.bucket_lds + (size_t)P.spb * (8 + sizeof(T)));
+            int* boff = bcnt + P.nb;
+            for (int64_t jb = w; jb < P.nblocks; jb += F.W) {
+                const int64_t s0 = jb * P.spb;
+                const int64_t c_end = std::min<int64_t>(P.nchunks, (s0 + P.spb) / 64);
+                for (int64_t chunk = s0 / 64 + wave; chunk < c_end; chunk += nwaves)
+                    lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, bkey, by, s0, true, T(1), lacc,
+                                                  step);
+                bucket_write_out<T, D>(P, jb, (int)std::min<int64_t>(P.spb, P.n - s0), bkey, by, bcnt, boff);
+            }
+        } else {
+            for (int64_t chunk = (int64_t)w * nwaves + wave; chunk < P.nchunks; chunk += (int64_t)F.W * nwaves)
+                lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, nullptr, nullptr, 0, false, T(1),
+                                              lacc, step);
+        }
         if (P.lds_mask) {
             // flush this workgroup's share of the small modes' gradient once
             __syncthreads();
@@ -138,6 +159,35 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
             }
         }
         fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+        if (P.bucket_mask) {
+            // each workgroup owns whole row blocks of the client: accumulate
+            // every segment list's entries for the block in LDS, then store
+            // it -- no other workgroup writes these rows of G_c
+            T* part = reinterpret_cast<T*>(smem);
+            int* seg_cnt = reinterpret_cast<int*>(
+                smem + ((((size_t)1 << P.br_shift) * P.R * sizeof(T) + 15) & ~(size_t)15));
+            constexpr int DM = D > 0 ? D : kMaxModes;
+            for (int rb = w; rb < P.nb; rb += F.W) {
+                // the row block's mode and rows, read with compile-time
+                // indices (keeps the parameter copy in registers)
+                int k = 0;
+                int64_t r0 = 0, rows = 0, roff = 0;
+#pragma unroll
+                for (int kk = 0; kk < DM; ++kk) {
+                    if (kk < dd && P.bucket_base[kk] <= rb && rb < P.bucket_base[kk + 1]) {
+                        k = kk;
+                        r0 = (int64_t)(rb - P.bucket_base[kk]) << P.br_shift;
+                        rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[kk] - r0);
+                        roff = P.rowoff[kk];
+                    }
+                }
+                bucket_accumulate<T, D, LANES, VEC>(P, k, rb, r0, rows, 0, P.nblocks, part, seg_cnt);
+                T* dst = G + (roff + r0) * P.R;
+                for (int64_t e = threadIdx.x; e < rows * P.R; e += blockDim.x) dst[e] = part[e];
+                __syncthreads();       // part is reused by the next row block
+            }
+            fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+        }
         const int64_t t = round * F.tau + j + 1;
         const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
         for (int64_t e = tid; e < nparams; e += nthreads) {
@@ -235,6 +285,8 @@ struct gcp_fed_s {
     const void* client_kernel = nullptr;
     size_t client_lds = 0;
     size_t lds_bytes = 0;          // private gradient copies of the batched kernel
+    size_t bucket_lds = 0;         // LDS the bucketed scatter needs (0 = not used)
+    void* bucket_ws = nullptr;     // sample entries, counts and starts of every client
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -296,6 +348,39 @@ static gcp_status fed_build(gcp_fed_s* f)
         lds_max_elems = used / (int64_t)sizeof(T);
     }
     f->lds_bytes = (size_t)lds_max_elems * sizeof(T);
+    const size_t staging = (size_t)(f->block / 64) * 64 * (8 + 2 * sizeof(T));
+
+    // row-bucketed modes of the batched kernel: a row block of 2^br_shift rows
+    // fills kFedBucketRowBytes of LDS; each client sorts its samples in blocks
+    // of spb into its own segment lists
+    uint32_t bucket_mask = 0;
+    int br_shift = 0, spb = 0;
+    int64_t nblocks_c = 0;
+    if (D.batched && D.bucket_modes > 0) bucket_mask = (uint32_t)D.bucket_modes & ((1u << d) - 1) & ~lds_mask;
+    std::vector<int64_t> ws_off(K + 1, 0);
+    std::vector<int> nb_c(K, 0);
+    int nbm = 0, nb_max = 0;
+    if (bucket_mask) {
+        while (((int64_t)2 << br_shift) * R * (int64_t)sizeof(T) <= kFedBucketRowBytes && br_shift < 30) ++br_shift;
+        spb = D.bucket_block_samples > 0 ? D.bucket_block_samples : 2048;
+        if (spb % 64 != 0 || spb < 512 || spb > 8192)
+            return set_error(GCP_ERR_ARG, "bucket_block_samples = %d", spb);
+        nblocks_c = ceil_div(D.p + D.q, spb);
+        for (int k = 0; k < d; ++k) nbm += (int)((bucket_mask >> k) & 1u);
+        for (int c = 0; c < K; ++c) {
+            const gcp_tensor_s* t = f->clients[c].tensor;
+            for (int k = 0; k < d; ++k)
+                if ((bucket_mask >> k) & 1u) nb_c[c] += (int)ceil_div(t->dims[k], int64_t(1) << br_shift);
+            nb_max = std::max(nb_max, nb_c[c]);
+            // entries, then counts and starts, 16-byte aligned per client
+            const int64_t bytes = nblocks_c * spb * nbm * 16 + (((int64_t)2 * nb_c[c] * nblocks_c * 4 + 15) & ~int64_t(15));
+            ws_off[c + 1] = ws_off[c] + bytes;
+        }
+        GCP_HIP(hipMalloc(&f->bucket_ws, (size_t)ws_off[K]));
+        const size_t phase1 = ((staging + f->lds_bytes + 15) & ~(size_t)15) + (size_t)spb * (8 + sizeof(T)) + (size_t)nb_max * 8;
+        const size_t phase2 = ((((size_t)1 << br_shift) * R * sizeof(T) + 15) & ~(size_t)15) + (size_t)nblocks_c * 8;
+        f->bucket_lds = std::max(phase1, phase2);
+    }
     for (int c = 0; c < K; ++c) {
         const gcp_fed_client& cl = f->clients[c];
         const gcp_tensor_s* t = cl.tensor;
@@ -328,6 +413,26 @@ static gcp_status fed_build(gcp_fed_s* f)
             }
         }
         h.P.lds_elems = off;
+        if (bucket_mask) {
+            h.P.bucket_mask = bucket_mask;
+            h.P.n_bucket_modes = nbm;
+            h.P.br_shift = br_shift;
+            h.P.nb = nb_c[c];
+            h.P.spb = spb;
+            h.P.nblocks = nblocks_c;
+            h.P.entry_cap = (int64_t)spb * nbm;
+            h.P.bucket_lds = (int)((staging + f->lds_bytes + 15) & ~(size_t)15);
+            int nb = 0;
+            for (int k = 0; k < d; ++k) {
+                h.P.bucket_base[k] = nb;
+                if ((bucket_mask >> k) & 1u) nb += (int)ceil_div(t->dims[k], int64_t(1) << br_shift);
+            }
+            for (int k = d; k <= kMaxModes; ++k) h.P.bucket_base[k] = nb;
+            unsigned char* base = (unsigned char*)f->bucket_ws + ws_off[c];
+            h.P.entries = (uint4*)base;
+            h.P.hist = (int*)(base + nblocks_c * spb * nbm * 16);
+            h.P.start = h.P.hist + (int64_t)nb_c[c] * nblocks_c;
+        }
         h.B = (T*)cl.B;
         h.C = (T*)cl.C;
         h.nparams = t->rowoff[d] * R;
@@ -398,8 +503,7 @@ static gcp_status fed_build(gcp_fed_s* f)
         if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "batched lane shape lanes = %d, vec = %d not built", f->lanes,
                                     f->vec);
         f->client_kernel = reinterpret_cast<const void*>(kern);
-        const size_t staging = (size_t)(f->block / 64) * 64 * (8 + 2 * sizeof(T));
-        f->client_lds = staging + f->lds_bytes;
+        f->client_lds = std::max(staging + f->lds_bytes, f->bucket_lds);
         reinterpret_cast<FedArgs<T>*>(f->args)->staging_bytes = (int)staging;
         st = prepare_lds(f->client_kernel, f->client_lds, f->device);
         if (st != GCP_OK) return st;
@@ -482,7 +586,7 @@ static void fed_free(gcp_fed_s* f)
     if (f->exec) (void)hipGraphExecDestroy(f->exec);
     if (f->graph) (void)hipGraphDestroy(f->graph);
     void* ptrs[] = {f->dev_clients, f->dev_mptrs, f->barrier, f->round, f->status, f->cov_ptr, f->cov_client,
-                    f->cov_lrow};
+                    f->cov_lrow, f->bucket_ws};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     (void)hipSetDevice(cur);

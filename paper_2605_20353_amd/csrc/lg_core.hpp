@@ -338,4 +338,158 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
     wave_sync();
 }
 
+// Bucketed scatter, sampling side: sorts the (key, y) of the workgroup's
+// nvalid staged samples (bkey, by in LDS) by (mode, row block) into segment
+// list `seg` of the bucket workspace -- count, scan, place -- and records the
+// list's per-bucket counts and starts.  Every thread of the workgroup calls it.
+template <typename T, int D>
+__device__ __forceinline__ void bucket_write_out(const LGParams<T>& P, int64_t seg, int nvalid, const uint64_t* bkey,
+                                                 const T* by, int* bcnt, int* boff)
+{
+    constexpr int DM = D > 0 ? D : kMaxModes;
+    const int dd = D > 0 ? D : P.sc.d;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    for (int b = threadIdx.x; b < P.nb; b += blockDim.x) bcnt[b] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
+        uint32_t ci[DM];
+        unpack_all<D == 0>(P.sc.L, dd, bkey[e], ci);
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < dd && ((P.bucket_mask >> k) & 1u)) atomicAdd(bcnt + P.bucket_base[k] + (int)(ci[k] >> P.br_shift), 1);
+    }
+    __syncthreads();
+    if (wave == 0) wave_exclusive_scan(bcnt, boff, P.nb, lane);
+    __syncthreads();
+    for (int b = threadIdx.x; b < P.nb; b += blockDim.x) {
+        P.hist[(int64_t)b * P.nblocks + seg] = bcnt[b];
+        P.start[(int64_t)b * P.nblocks + seg] = boff[b];
+    }
+    __syncthreads();
+    uint4* out = P.entries + seg * P.entry_cap;
+    for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
+        const uint64_t key = bkey[e];
+        const uint4 ent = pack_entry<T>(key, by[e]);
+        uint32_t ci[DM];
+        unpack_all<D == 0>(P.sc.L, dd, key, ci);
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            if (k < dd && ((P.bucket_mask >> k) & 1u)) {
+                const int pos = atomicAdd(boff + P.bucket_base[k] + (int)(ci[k] >> P.br_shift), 1);
+                out[pos] = ent;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Bucketed scatter, owner side: accumulates into `part` (LDS, rows x R) the
+// contributions y prod_{n != k} A_n[i_n, :] of every entry of bucket b (rows
+// [r0, r0 + rows) of mode k) in segment lists [j0, j1).  Each wave takes whole
+// segments in turn, loading the next pass's entries while it gathers the
+// other modes' rows; adds go through LDS compare-and-swap.  seg_cnt is LDS
+// scratch for 2 (j1 - j0) ints.  Every thread of the workgroup calls it; part
+// is complete when it returns.
+template <typename T, int D, int LANES, int VEC>
+__device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, int b, int64_t r0, int64_t rows,
+                                                  int64_t j0, int64_t j1, T* part, int* seg_cnt)
+{
+    constexpr int S = 64 / LANES;
+    constexpr int U = samples_in_flight<T, D, LANES, VEC>();
+    constexpr int DM = D > 0 ? D : kMaxModes;
+    static_assert(VEC == 1 || VEC == 2 || VEC == 4, "columns per lane");
+    const int nwaves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane / LANES, cl = lane % LANES;
+    const int col0 = cl * VEC;
+    const int R = P.R;
+    const bool col_ok = col0 < R;
+    const int dd = D > 0 ? D : P.sc.d;
+    // mode k's key field, selected with compile-time indices: a run-time
+    // index into the parameter block would force a register copy of it
+    // (the persistent FedAdam kernel holds one) out to scratch memory
+    int shift_k = 0;
+    uint64_t mask_k = 0;
+#pragma unroll
+    for (int kk = 0; kk < DM; ++kk)
+        if (kk == k) {
+            shift_k = P.sc.L.shift[kk];
+            mask_k = P.sc.L.mask[kk];
+        }
+    int* seg_start = seg_cnt + (j1 - j0);
+    for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) part[e] = T(0);
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+        seg_cnt[j - j0] = P.hist[(int64_t)b * P.nblocks + j];
+        seg_start[j - j0] = P.start[(int64_t)b * P.nblocks + j];
+    }
+    __syncthreads();
+
+    for (int64_t j = j0 + wave; j < j1; j += nwaves) {
+        const int cnt = seg_cnt[j - j0];
+        const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
+        // entries of the next pass are loaded while this pass gathers rows
+        uint4 nxt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = u * S + g;
+            nxt[u] = e < cnt ? seg[e] : make_uint4(0, 0, 0, 0);
+        }
+        for (int base = 0; base < cnt; base += S * U) {
+            uint64_t key[U];
+            T y[U];
+            T a[U][DM][VEC];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * S + g;
+                const bool valid = e < cnt;
+                const uint4 ent = nxt[u];
+                const int en = e + S * U;
+                nxt[u] = en < cnt ? seg[en] : make_uint4(0, 0, 0, 0);
+                key[u] = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
+                uint32_t ci[DM];
+                unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
+                y[u] = valid ? entry_y<T>(ent) : T(0);
+#pragma unroll
+                for (int kk = 0; kk < DM; ++kk) {
+                    if (kk < dd) {
+                        if (kk != k && col_ok && valid) {
+                            const uint64_t row = (uint64_t)P.rowoff[kk] + ci[kk];
+                            load_cols<T, VEC>(P.A + row_elem(row, R) + col0, a[u][kk]);
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v) a[u][kk][v] = T(1);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = base + u * S + g;
+                if (e >= cnt || !col_ok) continue;
+                uint32_t i;
+                if constexpr (D == 0) i = unpack_one<true, DM>(P.sc.L, dd, key[u], k);
+                else i = (uint32_t)((key[u] >> shift_k) & mask_k);
+                i -= (uint32_t)r0;
+                T c[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    c[v] = y[u];
+#pragma unroll
+                    for (int kk = 0; kk < DM; ++kk)
+                        if (kk < dd) c[v] *= a[u][kk][v];
+                }
+                T* dst = part + i * (uint32_t)R + col0;
+                lds_add(dst, c[0]);
+                if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
+                if constexpr (VEC > 2) {
+                    lds_add(dst + 2, c[2]);
+                    lds_add(dst + 3, c[3]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 }  // namespace gcp

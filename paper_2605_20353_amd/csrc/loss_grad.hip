@@ -97,44 +97,8 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
             }
         }
     }
-    if (tiled && !P.loss_only) {
-        // sort this workgroup's samples by (mode, row block) into its
-        // segment list: count, scan, place
-        __syncthreads();
-        const int nvalid = (int)std::min<int64_t>(P.spb, P.n - block_s0);
-        for (int b = threadIdx.x; b < P.nb; b += blockDim.x) bcnt[b] = 0;
-        __syncthreads();
-        for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
-            uint32_t ci[DM];
-            unpack_all<D == 0>(P.sc.L, dd, bkey[e], ci);
-#pragma unroll
-            for (int k = 0; k < DM; ++k)
-                if (k < dd && ((P.bucket_mask >> k) & 1u))
-                    atomicAdd(bcnt + P.bucket_base[k] + (int)(ci[k] >> P.br_shift), 1);
-        }
-        __syncthreads();
-        if (wave == 0) wave_exclusive_scan(bcnt, boff, P.nb, lane);
-        __syncthreads();
-        for (int b = threadIdx.x; b < P.nb; b += blockDim.x) {
-            P.hist[(int64_t)b * P.nblocks + blockIdx.x] = bcnt[b];
-            P.start[(int64_t)b * P.nblocks + blockIdx.x] = boff[b];
-        }
-        __syncthreads();
-        uint4* seg = P.entries + (int64_t)blockIdx.x * P.entry_cap;
-        for (int e = threadIdx.x; e < nvalid; e += blockDim.x) {
-            const uint64_t key = bkey[e];
-            const uint4 ent = pack_entry<T>(key, by[e]);
-            uint32_t ci[DM];
-            unpack_all<D == 0>(P.sc.L, dd, key, ci);
-#pragma unroll
-            for (int k = 0; k < DM; ++k) {
-                if (k < dd && ((P.bucket_mask >> k) & 1u)) {
-                    const int pos = atomicAdd(boff + P.bucket_base[k] + (int)(ci[k] >> P.br_shift), 1);
-                    seg[pos] = ent;
-                }
-            }
-        }
-    }
+    if (tiled && !P.loss_only)
+        bucket_write_out<T, D>(P, blockIdx.x, (int)std::min<int64_t>(P.spb, P.n - block_s0), bkey, by, bcnt, boff);
 }
 
 // Row-block owner pass of the bucketed scatter.  Workgroup (b, split) owns
@@ -145,18 +109,9 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
 template <typename T, int D, int LANES, int VEC>
 __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
 {
-    constexpr int S = 64 / LANES;
-    constexpr int U = samples_in_flight<T, D, LANES, VEC>();
-    constexpr int DM = D > 0 ? D : kMaxModes;
-    static_assert(VEC == 1 || VEC == 2 || VEC == 4, "columns per lane");
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     T* part = reinterpret_cast<T*>(smem);
-    const int nwaves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane / LANES, cl = lane % LANES;
-    const int col0 = cl * VEC;
     const int R = P.R;
-    const bool col_ok = col0 < R;
     const int dd = D > 0 ? D : P.sc.d;
 
     // the mode whose workgroup range holds this workgroup (ranges of modes
@@ -174,78 +129,8 @@ __global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
     // waves per workgroup); the last split takes the remainder
     const int64_t j0 = (int64_t)split * P.bsegs[k];
     const int64_t j1 = std::min<int64_t>(P.nblocks, j0 + P.bsegs[k]);
-    // this row block's segment counts and starts for workgroups [j0, j1),
-    // staged once in LDS after the row block
     int* seg_cnt = reinterpret_cast<int*>(smem + (((size_t)rows * R * sizeof(T) + 15) & ~(size_t)15));
-    int* seg_start = seg_cnt + (j1 - j0);
-    for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) part[e] = T(0);
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-        seg_cnt[j - j0] = P.hist[(int64_t)b * P.nblocks + j];
-        seg_start[j - j0] = P.start[(int64_t)b * P.nblocks + j];
-    }
-    __syncthreads();
-
-    for (int64_t j = j0 + wave; j < j1; j += nwaves) {
-        const int cnt = seg_cnt[j - j0];
-        const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
-        // entries of the next pass are loaded while this pass gathers rows
-        uint4 nxt[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = u * S + g;
-            nxt[u] = e < cnt ? seg[e] : make_uint4(0, 0, 0, 0);
-        }
-        for (int base = 0; base < cnt; base += S * U) {
-            uint64_t key[U];
-            T y[U];
-            T a[U][DM][VEC];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = base + u * S + g;
-                const bool valid = e < cnt;
-                const uint4 ent = nxt[u];
-                const int en = e + S * U;
-                nxt[u] = en < cnt ? seg[en] : make_uint4(0, 0, 0, 0);
-                key[u] = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
-                uint32_t ci[DM];
-                unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
-                y[u] = valid ? entry_y<T>(ent) : T(0);
-#pragma unroll
-                for (int kk = 0; kk < DM; ++kk) {
-                    if (kk < dd) {
-                        if (kk != k && col_ok && valid) {
-                            const uint64_t row = (uint64_t)P.rowoff[kk] + ci[kk];
-                            load_cols<T, VEC>(P.A + row_elem(row, R) + col0, a[u][kk]);
-                        } else {
-#pragma unroll
-                            for (int v = 0; v < VEC; ++v) a[u][kk][v] = T(1);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = base + u * S + g;
-                if (e >= cnt || !col_ok) continue;
-                const uint32_t i = unpack_one<D == 0, DM>(P.sc.L, dd, key[u], k) - (uint32_t)r0;
-                T c[VEC];
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) {
-                    c[v] = y[u];
-#pragma unroll
-                    for (int kk = 0; kk < DM; ++kk)
-                        if (kk < dd) c[v] *= a[u][kk][v];
-                }
-                T* dst = part + i * (uint32_t)R + col0;
-                lds_add(dst, c[0]);
-                if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
-                if constexpr (VEC > 2) {
-                    lds_add(dst + 2, c[2]);
-                    lds_add(dst + 3, c[3]);
-                }
-            }
-        }
-    }
+    bucket_accumulate<T, D, LANES, VEC>(P, k, b, r0, rows, j0, j1, part, seg_cnt);
     __syncthreads();
     T* dst = P.G + (P.rowoff[k] + r0) * R;
     for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) {

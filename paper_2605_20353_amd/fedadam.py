@@ -26,7 +26,8 @@ class gcp_fed_desc(C.Structure):
     _fields_ = [("nclients", C.c_int32), ("R", C.c_int32), ("tau", C.c_int32), ("loss", C.c_int32),
                 ("batched", C.c_int32), ("use_graph", C.c_int32), ("workgroups_per_client", C.c_int32),
                 ("block", C.c_int32), ("lanes", C.c_int32), ("vec", C.c_int32), ("max_attempts", C.c_int32),
-                ("lds_modes", C.c_int32), ("p", C.c_int64), ("q", C.c_int64), ("seed", C.c_uint64),
+                ("lds_modes", C.c_int32), ("bucket_modes", C.c_int32), ("bucket_block_samples", C.c_int32),
+                ("p", C.c_int64), ("q", C.c_int64), ("seed", C.c_uint64),
                 ("global_dims", C.c_int64 * 8), ("U", C.c_void_p), ("Bs", C.c_void_p), ("Cs", C.c_void_p),
                 ("lr", C.c_double), ("meta_lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
                 ("eps", C.c_double), ("lower", C.c_double), ("clients", C.POINTER(gcp_fed_client))]
@@ -73,9 +74,12 @@ class FedTile:
     lanes: int = 0
     vec: int = 0
     lds_modes: int = -1
+    bucket_modes: int = 0          # bitmask of row-bucketed modes (0: hardware atomics)
+    bucket_block_samples: int = 0
 
     def key(self):
-        return (self.workgroups_per_client, self.block, self.lanes, self.vec, self.lds_modes)
+        return (self.workgroups_per_client, self.block, self.lanes, self.vec, self.lds_modes, self.bucket_modes,
+                self.bucket_block_samples)
 
 
 @dataclass
@@ -141,6 +145,8 @@ class FedAdam:
         d.vec = self.tile.vec
         d.max_attempts = cfg.max_attempts
         d.lds_modes = self.tile.lds_modes
+        d.bucket_modes = self.tile.bucket_modes
+        d.bucket_block_samples = self.tile.bucket_block_samples
         d.p, d.q, d.seed = cfg.p, cfg.q, cfg.seed
         for k, n in enumerate(self.global_dims):
             d.global_dims[k] = n

@@ -62,14 +62,24 @@ def _rel(a, b):
 SMALL = dict(gdims=[40, 36, 20], grid=(2, 2, 2), R=3, nmin=30, nmax=150)
 
 
-@pytest.mark.parametrize("mode", ["batched_graph", "batched", "plain"])
+# batched variants of the gradient scatter: atomics (default for few samples),
+# every mode row-bucketed, and an LDS-private mode next to bucketed ones
+SCATTER = {"atomic": FedTile(), "bucketed": FedTile(lds_modes=0, bucket_modes=7),
+           "lds_and_bucketed": FedTile(lds_modes=4, bucket_modes=3)}
+
+
+@pytest.mark.parametrize("mode", ["batched_graph", "batched", "plain", "batched_graph_bucketed", "batched_bucketed",
+                                  "batched_graph_lds_and_bucketed"])
 def test_fp64_rounds_match_oracle(gpu, mode):
     gdims, R = SMALL["gdims"], SMALL["R"]
     blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2609)
     U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2709, dtype=torch.float64)
     cfg = FedConfig(R=R, tau=3, loss="poisson", p=64, q=64, seed=20353, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    scatter = "lds_and_bucketed" if mode.endswith("lds_and_bucketed") else (
+        "bucketed" if mode.endswith("bucketed") else "atomic")
+    say(f"fedadam fp64 {mode}")
     fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg,
-                  batched=mode != "plain", use_graph=mode == "batched_graph")
+                  batched=mode != "plain", use_graph=mode.startswith("batched_graph"), tile=SCATTER[scatter])
     for r in range(2):
         fed.round(r)
     fed.status()
@@ -95,26 +105,48 @@ def test_fp64_workgroups_per_client_sweep(gpu):
         fed.close()
 
 
+@pytest.mark.parametrize("tile", [FedTile(1, 64, lds_modes=0, bucket_modes=7, bucket_block_samples=512),
+                                  FedTile(3, 128, lds_modes=0, bucket_modes=7, bucket_block_samples=512),
+                                  FedTile(4, 1024, lds_modes=4, bucket_modes=3, bucket_block_samples=1024)])
+def test_fp64_bucketed_blocks_and_workgroups(gpu, tile):
+    """Several sorted sample blocks per client step, spread over 1..4
+    workgroups per client, with ragged last blocks, against the oracle."""
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], 400, seed=2612)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2712, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=1500, q=1301, seed=7, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0, cfg, 2, torch.float64)
+    say(f"fedadam bucketed {tile}")
+    fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, tile=tile)
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10
+    for cl, oc in zip(fed.clients, ocl):
+        assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
+
+
 @pytest.mark.parametrize("shape", [(32, 1), (16, 2), (8, 4)])
 def test_fp32_batched_equals_plain_and_oracle(gpu, shape):
     gdims, grid, R = [200, 160, 60], (4, 2, 2), 32
     blocks = _blocks(gdims, grid, R, 200, 2000, seed=2611)
     U0 = 0.1 + 0.9 * synth.init_model(gdims, R, 2711, dtype=torch.float64)
     cfg = FedConfig(R=R, tau=4, loss="poisson", p=1024, q=1024, seed=11, lr=1e-3, meta_lr=1e-3, lower=0.0)
-    tile = FedTile(lanes=shape[0], vec=shape[1])
     feds = {}
-    for mode in ("batched_graph", "plain"):
+    for mode in ("batched_graph", "plain", "batched_graph_bucketed"):
+        tile = FedTile(lanes=shape[0], vec=shape[1], bucket_modes=7 if mode.endswith("bucketed") else 0)
         fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg,
-                      batched=mode != "plain", use_graph=mode == "batched_graph", tile=tile)
+                      batched=mode != "plain", use_graph=mode.startswith("batched_graph"), tile=tile)
         for r in range(2):
             fed.round(r)
         fed.status()
         feds[mode] = fed
-    Ub = feds["batched_graph"].U.double().cpu().numpy()
     Up = feds["plain"].U.double().cpu().numpy()
-    assert _rel(Ub, Up) <= 1e-5
     Uo, _ = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
-    assert _rel(Ub, Uo) <= 1e-5
+    for mode in ("batched_graph", "batched_graph_bucketed"):
+        Ub = feds[mode].U.double().cpu().numpy()
+        assert _rel(Ub, Up) <= 1e-5, mode
+        assert _rel(Ub, Uo) <= 1e-5, mode
 
 
 def test_graph_replays_stay_exact(gpu):

@@ -8,8 +8,9 @@ GPU's hash table), and the whole gradient of the fused kernel -- atomic and
 row-bucketed scatter -- against the oracle's gradient on its own samples.
 
 GCP-FedAdam, 64 clients on a 4 x 4 x 4 grid over 20000 x 20000 x 2000 with
-1e5..5e6 nonzeros per client: one batched (graph-replayed) round equals one
-round of per-client launches.
+1e5..5e6 nonzeros per client: one batched (graph-replayed) round, with the
+atomic and with the row-bucketed scatter, equals one round of per-client
+launches.
 """
 import sys
 import time
@@ -21,7 +22,7 @@ import torch
 import oracle
 from paper_2605_20353_amd import _lib as G
 from paper_2605_20353_amd import synth
-from paper_2605_20353_amd.fedadam import FedAdam, FedConfig
+from paper_2605_20353_amd.fedadam import FedAdam, FedConfig, FedTile
 
 pytestmark = pytest.mark.gpu
 
@@ -78,13 +79,17 @@ def test_config5_full_size_batched_equals_plain(gpu):
     cfg = FedConfig(R=R, tau=10, loss="poisson", p=1 << 16, q=1 << 16, seed=20353, lr=1e-3, meta_lr=1e-3,
                     lower=0.0)
     Us = {}
-    for name, kw in (("plain", dict(batched=False)), ("graph", dict(batched=True, use_graph=True))):
+    modes = (("plain", dict(batched=False)), ("graph", dict(batched=True, use_graph=True)),
+             ("graph_bucketed", dict(batched=True, use_graph=True, tile=FedTile(block=1024, lanes=8, vec=4,
+                                                                                  bucket_modes=7))))
+    for name, kw in modes:
         fed = FedAdam(clients, gd, U0, cfg, **kw)
         fed.round(0)
         fed.status()
         Us[name] = fed.U.double().cpu().numpy()
         say(f"config 5: {name} round done")
         fed.close()
-    rel = np.linalg.norm(Us["graph"] - Us["plain"]) / np.linalg.norm(Us["plain"])
-    assert rel <= 1e-5, rel
+    for name in ("graph", "graph_bucketed"):      # atomic and row-bucketed scatter
+        rel = np.linalg.norm(Us[name] - Us["plain"]) / np.linalg.norm(Us["plain"])
+        assert rel <= 1e-5, (name, rel)
     assert np.abs(Us["graph"] - U0.double().cpu().numpy().reshape(-1)).max() > 0     # the round moved U
