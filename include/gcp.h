@@ -274,7 +274,8 @@ typedef struct gcp_fed_desc {
     int32_t use_graph;        /* batched only: capture the round's launches into
                                  a HIP graph on the first round, replay after     */
     int32_t workgroups_per_client; /* batched launch shape, 0 = automatic        */
-    int32_t block;            /* threads per workgroup (batched), 0 = 256         */
+    int32_t block;            /* threads per workgroup (batched), 0 = 256 (1024
+                                 for row-bucketed rounds)                         */
     int32_t lanes;            /* lane shape of the gradient part, 0 = default    */
     int32_t vec;
     int32_t max_attempts;     /* rejection attempts per zero sample, <= 0 = 64   */
@@ -287,10 +288,14 @@ typedef struct gcp_fed_desc {
                                  each client's workgroups sort their samples by
                                  row block, then each owns whole row blocks and
                                  writes them without atomics (modes that are
-                                 LDS-private are left out); 0 or -1 = none, the
-                                 hardware-atomic scatter, which measured faster
-                                 in the persistent launch (its LDS leaves one
-                                 workgroup per CU)                              */
+                                 LDS-private are left out).  Such rounds run as
+                                 three launches per local step over all clients
+                                 (sample and sort, row-block owners, Adam)
+                                 instead of the persistent launch; default
+                                 block 1024 and, in FP32, four columns per lane.
+                                 -1 = automatic: every mode that is not LDS-
+                                 private at >= 2^14 samples per client step,
+                                 else none; 0 = none (hardware atomics)         */
     int32_t bucket_block_samples; /* samples per sorted block, multiple of 64 in
                                  [512, 8192]; 0 = 2048                            */
     int64_t p;                /* nonzero samples per client and local step       */

@@ -62,10 +62,10 @@ def _time(fn, stream, reps: int, warmup: int) -> float:
 # ------------------------------------------------------------ FedAdam round --
 
 def fed_candidates(R: int, dtype, nclients: int, cus: int = 256, nmodes: int = 3):
-    """Launch shapes worth trying for a batched round: atomic scatter over
-    lane shapes, workgroup sizes and workgroups per client, then the
-    row-bucketed scatter (whose LDS keeps about one workgroup per CU) over
-    lane shapes and workgroup sizes."""
+    """Launch shapes worth trying for a batched round: the persistent launch
+    with the atomic scatter over lane shapes, workgroup sizes and workgroups
+    per client, then the row-bucketed rounds (three launches per local step)
+    over lane shapes (0 = its default) and workgroup sizes."""
     shapes = [(32, 1), (16, 2)] if R == 32 else [(0, 0)]
     if dtype == torch.float32 and R == 32:
         shapes.append((8, 4))
@@ -79,7 +79,7 @@ def fed_candidates(R: int, dtype, nclients: int, cus: int = 256, nmodes: int = 3
                 out.append(FedTile(workgroups_per_client=w, block=block, lanes=lanes, vec=vec, bucket_modes=0))
     all_modes = (1 << nmodes) - 1
     for block in (512, 1024):
-        for lanes, vec in shapes:
+        for lanes, vec in shapes + [(0, 0)]:
             out.append(FedTile(workgroups_per_client=0, block=block, lanes=lanes, vec=vec, bucket_modes=all_modes))
     return out
 

@@ -6,10 +6,14 @@
 // copy the client's rows of the server model into M_c, then for each of the
 // tau local steps: the sampled gradient of the client's block (the same
 // per-chunk body as gcp_loss_grad; small modes accumulate in LDS, large ones
-// either with hardware atomics into G_c or row-bucketed: the workgroups sort
-// their samples by row block, and after a group barrier each owns whole row
-// blocks, accumulates them in LDS and stores them into G_c), a group barrier,
-// Adam on M_c (which also re-zeroes G_c), a group barrier.  The
+// with hardware atomics into G_c), a group barrier, Adam on M_c (which also
+// re-zeroes G_c), a group barrier.
+//
+// Batched rounds with the row-bucketed scatter instead run, per local step,
+// three launches that each cover every client (blockIdx.y = client): sample
+// and sort by row block (k_fed_sample), row-block owners that accumulate in
+// LDS and store their rows of G_c (k_fed_owner), and Adam (k_fed_adam); the
+// kernel boundaries take the place of the group barriers.  The
 // barrier is a per-client arrival counter in global memory with bounded
 // spinning: all K*W workgroups must be resident (checked at create), and a
 // barrier that waits too long records an error instead of hanging.
@@ -28,6 +32,7 @@ constexpr uint32_t kStatusBarrier = 4u;
 constexpr long kSpinLimit = 1L << 22;
 constexpr int kFedLdsBudget = 64 * 1024;   // bytes of private client gradient per workgroup
 constexpr int kFedBucketRowBytes = 32 * 1024;   // LDS of one row block in the bucketed scatter
+constexpr int64_t kFedBucketMinSamples = 1 << 14;   // automatic bucketing from this many samples per client step
 
 template <typename T>
 struct FedClientDev {
@@ -124,26 +129,9 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
             for (int64_t e = threadIdx.x; e < P.lds_elems; e += blockDim.x) priv[e] = T(0);
             __syncthreads();
         }
-        if (P.bucket_mask) {
-            // blocks of spb samples, each sorted by row block into this
-            // client's segment list of the same index
-            uint64_t* bkey = reinterpret_cast<uint64_t*>(smem + P.bucket_lds);
-            T* by = reinterpret_cast<T*>(smem + P.bucket_lds + (size_t)P.spb * 8);
-            int* bcnt = reinterpret_cast<int*>(smem + P.bucket_lds + (size_t)P.spb * (8 + sizeof(T)));
-            int* boff = bcnt + P.nb;
-            for (int64_t jb = w; jb < P.nblocks; jb += F.W) {
-                const int64_t s0 = jb * P.spb;
-                const int64_t c_end = std::min<int64_t>(P.nchunks, (s0 + P.spb) / 64);
-                for (int64_t chunk = s0 / 64 + wave; chunk < c_end; chunk += nwaves)
-                    lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, bkey, by, s0, true, T(1), lacc,
-                                                  step);
-                bucket_write_out<T, D>(P, jb, (int)std::min<int64_t>(P.spb, P.n - s0), bkey, by, bcnt, boff);
-            }
-        } else {
-            for (int64_t chunk = (int64_t)w * nwaves + wave; chunk < P.nchunks; chunk += (int64_t)F.W * nwaves)
-                lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, nullptr, nullptr, 0, false, T(1),
-                                              lacc, step);
-        }
+        for (int64_t chunk = (int64_t)w * nwaves + wave; chunk < P.nchunks; chunk += (int64_t)F.W * nwaves)
+            lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, nullptr, nullptr, 0, false, T(1),
+                                          lacc, step);
         if (P.lds_mask) {
             // flush this workgroup's share of the small modes' gradient once
             __syncthreads();
@@ -159,35 +147,6 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
             }
         }
         fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
-        if (P.bucket_mask) {
-            // each workgroup owns whole row blocks of the client: accumulate
-            // every segment list's entries for the block in LDS, then store
-            // it -- no other workgroup writes these rows of G_c
-            T* part = reinterpret_cast<T*>(smem);
-            int* seg_cnt = reinterpret_cast<int*>(
-                smem + ((((size_t)1 << P.br_shift) * P.R * sizeof(T) + 15) & ~(size_t)15));
-            constexpr int DM = D > 0 ? D : kMaxModes;
-            for (int rb = w; rb < P.nb; rb += F.W) {
-                // the row block's mode and rows, read with compile-time
-                // indices (keeps the parameter copy in registers)
-                int k = 0;
-                int64_t r0 = 0, rows = 0, roff = 0;
-#pragma unroll
-                for (int kk = 0; kk < DM; ++kk) {
-                    if (kk < dd && P.bucket_base[kk] <= rb && rb < P.bucket_base[kk + 1]) {
-                        k = kk;
-                        r0 = (int64_t)(rb - P.bucket_base[kk]) << P.br_shift;
-                        rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[kk] - r0);
-                        roff = P.rowoff[kk];
-                    }
-                }
-                bucket_accumulate<T, D, LANES, VEC>(P, k, rb, r0, rows, 0, P.nblocks, part, seg_cnt);
-                T* dst = G + (roff + r0) * P.R;
-                for (int64_t e = threadIdx.x; e < rows * P.R; e += blockDim.x) dst[e] = part[e];
-                __syncthreads();       // part is reused by the next row block
-            }
-            fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
-        }
         const int64_t t = round * F.tau + j + 1;
         const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
         for (int64_t e = tid; e < nparams; e += nthreads) {
@@ -199,6 +158,111 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
             G[e] = T(0);
         }
         if (j + 1 < F.tau) fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+    }
+}
+
+// Bucketed batched round, sampling side.  Workgroup (x, c) takes client c's
+// sample blocks x, x + gridDim.x, ...: draws and stages each block's
+// samples, forms model values and derivatives, accumulates the small modes in
+// its LDS, and sorts the block by row block into the client's segment list
+// of the same index; the small modes are flushed into G_c once at the end.
+template <typename T, int D, int LANES, int VEC>
+__global__ void __launch_bounds__(1024) k_fed_sample(const FedArgs<T> F, int j)
+{
+    constexpr int DM = D > 0 ? D : kMaxModes;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const LGParams<T> P = F.clients[blockIdx.y].P;
+    const int nwaves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint64_t* skey = reinterpret_cast<uint64_t*>(smem) + wave * 64;
+    T* sx = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * 8) + wave * 64;
+    T* sw = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * (8 + sizeof(T))) + wave * 64;
+    T* priv = reinterpret_cast<T*>(smem + F.staging_bytes);
+    uint64_t* bkey = reinterpret_cast<uint64_t*>(smem + P.bucket_lds);
+    T* by = reinterpret_cast<T*>(smem + P.bucket_lds + (size_t)P.spb * 8);
+    int* bcnt = reinterpret_cast<int*>(smem + P.bucket_lds + (size_t)P.spb * (8 + sizeof(T)));
+    int* boff = bcnt + P.nb;
+    const int dd = D > 0 ? D : P.sc.d;
+    const uint64_t step = (uint64_t)(*F.round * F.tau + j);
+    double lacc = 0.0;
+    if (P.lds_mask) {
+        for (int64_t e = threadIdx.x; e < P.lds_elems; e += blockDim.x) priv[e] = T(0);
+        __syncthreads();
+    }
+    for (int64_t jb = blockIdx.x; jb < P.nblocks; jb += gridDim.x) {
+        const int64_t s0 = jb * P.spb;
+        const int64_t c_end = std::min<int64_t>(P.nchunks, (s0 + P.spb) / 64);
+        for (int64_t chunk = s0 / 64 + wave; chunk < c_end; chunk += nwaves)
+            lg_chunk<T, D, LANES, VEC, 0>(P, chunk, lane, skey, sx, sw, priv, bkey, by, s0, true, T(1), lacc, step);
+        bucket_write_out<T, D>(P, jb, (int)std::min<int64_t>(P.spb, P.n - s0), bkey, by, bcnt, boff);
+    }
+    if (P.lds_mask) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DM; ++k) {
+            if (k < dd && ((P.lds_mask >> k) & 1u)) {
+                const int64_t elems = P.sc.L.dims[k] * (int64_t)P.R;
+                T* dst = P.G + P.rowoff[k] * P.R;
+                const T* src = priv + P.lds_off[k];
+                for (int64_t e = threadIdx.x; e < elems; e += blockDim.x) {
+                    const T v = src[e];
+                    if (v != T(0)) global_add(dst + e, v);
+                }
+            }
+        }
+    }
+}
+
+// Bucketed batched round, owner side.  Workgroup (rb, c) owns row block rb of
+// client c's bucketed modes: it accumulates the entries of every segment list
+// for the block in LDS and stores the rows into G_c -- no other workgroup
+// writes them.
+template <typename T, int D, int LANES, int VEC>
+__global__ void __launch_bounds__(1024) k_fed_owner(const FedArgs<T> F)
+{
+    constexpr int DM = D > 0 ? D : kMaxModes;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const LGParams<T> P = F.clients[blockIdx.y].P;
+    const int rb = blockIdx.x;
+    if (rb >= P.nb) return;
+    const int dd = D > 0 ? D : P.sc.d;
+    // the row block's mode and rows, read with compile-time indices
+    int k = 0;
+    int64_t r0 = 0, rows = 0, roff = 0;
+#pragma unroll
+    for (int kk = 0; kk < DM; ++kk) {
+        if (kk < dd && P.bucket_base[kk] <= rb && rb < P.bucket_base[kk + 1]) {
+            k = kk;
+            r0 = (int64_t)(rb - P.bucket_base[kk]) << P.br_shift;
+            rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[kk] - r0);
+            roff = P.rowoff[kk];
+        }
+    }
+    T* part = reinterpret_cast<T*>(smem);
+    int* seg_cnt = reinterpret_cast<int*>(smem + ((((size_t)1 << P.br_shift) * P.R * sizeof(T) + 15) & ~(size_t)15));
+    bucket_accumulate<T, D, LANES, VEC>(P, k, rb, r0, rows, 0, P.nblocks, part, seg_cnt);
+    T* dst = P.G + (roff + r0) * P.R;
+    for (int64_t e = threadIdx.x; e < rows * P.R; e += blockDim.x) dst[e] = part[e];
+}
+
+// Adam on every client's model (blockIdx.y = client) for local step j,
+// re-zeroing G_c.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fed_adam(const FedArgs<T> F, int j)
+{
+    const FedClientDev<T>& C = F.clients[blockIdx.y];
+    T* M = const_cast<T*>(C.P.A);
+    T* G = C.P.G;
+    const int64_t t = *F.round * F.tau + j + 1;
+    const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
+    const int64_t n = C.nparams;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        T p = M[e], b = C.B[e], cc = C.C[e];
+        adam_update<T>(p, G[e], b, cc, F.lr, F.b1, F.b2, F.one_m_b1, F.one_m_b2, c1, c2, F.eps, F.lower);
+        M[e] = p;
+        C.B[e] = b;
+        C.C[e] = cc;
+        G[e] = T(0);
     }
 }
 
@@ -243,6 +307,8 @@ __global__ void k_fed_set_round(int64_t* round, int64_t value) { *round = value;
 
 template <typename T>
 using FedKernel = void (*)(const FedArgs<T>);
+template <typename T>
+using FedStepKernel = void (*)(const FedArgs<T>, int);
 
 #define GCP_FED_SHAPES_F32(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(16, 2) X(32, 2) X(8, 4) X(16, 4)
 #define GCP_FED_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(16, 2) X(32, 2)
@@ -252,6 +318,34 @@ static FedKernel<T> pick_fed(int lanes, int vec)
 {
 #define GCP_CASE(LN, VC) \
     if (lanes == LN && vec == VC) return k_fed_clients<T, D, LN, VC>;
+    if constexpr (sizeof(T) == 4) {
+        GCP_FED_SHAPES_F32(GCP_CASE)
+    } else {
+        GCP_FED_SHAPES_F64(GCP_CASE)
+    }
+#undef GCP_CASE
+    return nullptr;
+}
+
+template <typename T, int D>
+static FedStepKernel<T> pick_fed_sample(int lanes, int vec)
+{
+#define GCP_CASE(LN, VC) \
+    if (lanes == LN && vec == VC) return k_fed_sample<T, D, LN, VC>;
+    if constexpr (sizeof(T) == 4) {
+        GCP_FED_SHAPES_F32(GCP_CASE)
+    } else {
+        GCP_FED_SHAPES_F64(GCP_CASE)
+    }
+#undef GCP_CASE
+    return nullptr;
+}
+
+template <typename T, int D>
+static FedKernel<T> pick_fed_owner(int lanes, int vec)
+{
+#define GCP_CASE(LN, VC) \
+    if (lanes == LN && vec == VC) return k_fed_owner<T, D, LN, VC>;
     if constexpr (sizeof(T) == 4) {
         GCP_FED_SHAPES_F32(GCP_CASE)
     } else {
@@ -285,8 +379,16 @@ struct gcp_fed_s {
     const void* client_kernel = nullptr;
     size_t client_lds = 0;
     size_t lds_bytes = 0;          // private gradient copies of the batched kernel
-    size_t bucket_lds = 0;         // LDS the bucketed scatter needs (0 = not used)
+    // row-bucketed batched rounds: per local step one sampling, one owner and
+    // one Adam launch over all clients
+    bool want_bucket = false;      // the description asks for (or defaults to) bucketing
+    bool bucketed = false;
     void* bucket_ws = nullptr;     // sample entries, counts and starts of every client
+    const void* sample_kernel = nullptr;
+    const void* owner_kernel = nullptr;
+    size_t sample_lds = 0, owner_lds = 0;
+    int nb_max = 0;                // row blocks of the largest client
+    int64_t max_params = 0;        // parameters of the largest client
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -356,7 +458,10 @@ static gcp_status fed_build(gcp_fed_s* f)
     uint32_t bucket_mask = 0;
     int br_shift = 0, spb = 0;
     int64_t nblocks_c = 0;
-    if (D.batched && D.bucket_modes > 0) bucket_mask = (uint32_t)D.bucket_modes & ((1u << d) - 1) & ~lds_mask;
+    if (f->want_bucket) {
+        const uint32_t all = (1u << d) - 1;
+        bucket_mask = (D.bucket_modes > 0 ? (uint32_t)D.bucket_modes : all) & all & ~lds_mask;
+    }
     std::vector<int64_t> ws_off(K + 1, 0);
     std::vector<int> nb_c(K, 0);
     int nbm = 0, nb_max = 0;
@@ -376,10 +481,11 @@ static gcp_status fed_build(gcp_fed_s* f)
             const int64_t bytes = nblocks_c * spb * nbm * 16 + (((int64_t)2 * nb_c[c] * nblocks_c * 4 + 15) & ~int64_t(15));
             ws_off[c + 1] = ws_off[c] + bytes;
         }
-        GCP_HIP(hipMalloc(&f->bucket_ws, (size_t)ws_off[K]));
-        const size_t phase1 = ((staging + f->lds_bytes + 15) & ~(size_t)15) + (size_t)spb * (8 + sizeof(T)) + (size_t)nb_max * 8;
-        const size_t phase2 = ((((size_t)1 << br_shift) * R * sizeof(T) + 15) & ~(size_t)15) + (size_t)nblocks_c * 8;
-        f->bucket_lds = std::max(phase1, phase2);
+        GCP_HIP(hipMalloc(&f->bucket_ws, (size_t)std::max<int64_t>(16, ws_off[K])));
+        f->bucketed = true;
+        f->nb_max = nb_max;
+        f->sample_lds = ((staging + f->lds_bytes + 15) & ~(size_t)15) + (size_t)spb * (8 + sizeof(T)) + (size_t)nb_max * 8;
+        f->owner_lds = ((((size_t)1 << br_shift) * R * sizeof(T) + 15) & ~(size_t)15) + (size_t)nblocks_c * 8;
     }
     for (int c = 0; c < K; ++c) {
         const gcp_fed_client& cl = f->clients[c];
@@ -436,6 +542,7 @@ static gcp_status fed_build(gcp_fed_s* f)
         h.B = (T*)cl.B;
         h.C = (T*)cl.C;
         h.nparams = t->rowoff[d] * R;
+        f->max_params = std::max<int64_t>(f->max_params, h.nparams);
         for (int k = 0; k < kMaxModes; ++k) {
             h.seg_src[k] = k < d ? (goff[k] + cl.row_base[k]) * R : 0;
             h.seg_dst[k] = k < d ? t->rowoff[k] * R : 0;
@@ -493,17 +600,39 @@ static gcp_status fed_build(gcp_fed_s* f)
     a.Mptrs = (T* const*)f->dev_mptrs;
     memcpy(f->args, &a, sizeof(a));
 
+    bool order3 = d == 3;
+    for (const gcp_fed_client& cl : f->clients) order3 = order3 && kernel_order(cl.tensor) == 3;
+    if (D.batched && f->bucketed) {
+        reinterpret_cast<FedArgs<T>*>(f->args)->staging_bytes = (int)staging;
+        FedStepKernel<T> sk = order3 ? pick_fed_sample<T, 3>(f->lanes, f->vec) : pick_fed_sample<T, 0>(f->lanes, f->vec);
+        FedKernel<T> ok = order3 ? pick_fed_owner<T, 3>(f->lanes, f->vec) : pick_fed_owner<T, 0>(f->lanes, f->vec);
+        if (!sk || !ok)
+            return set_error(GCP_ERR_UNSUPPORTED, "batched lane shape lanes = %d, vec = %d not built", f->lanes, f->vec);
+        f->sample_kernel = reinterpret_cast<const void*>(sk);
+        f->owner_kernel = reinterpret_cast<const void*>(ok);
+        gcp_status st = prepare_lds(f->sample_kernel, f->sample_lds, f->device);
+        if (st != GCP_OK) return st;
+        st = prepare_lds(f->owner_kernel, f->owner_lds, f->device);
+        if (st != GCP_OK) return st;
+        if (D.workgroups_per_client <= 0) {
+            // automatic: the sampling launch fills the GPU once
+            int per_cu = 0;
+            GCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f->sample_kernel, f->block, f->sample_lds));
+            const int64_t resident = (int64_t)std::max(1, per_cu) * device_cu_count(f->device);
+            f->W = (int)std::max<int64_t>(1, std::min<int64_t>(nblocks_c, resident / K));
+            reinterpret_cast<FedArgs<T>*>(f->args)->W = f->W;
+        }
+        return GCP_OK;
+    }
     if (D.batched) {
         gcp_status st = GCP_OK;
         FedKernel<T> kern = nullptr;
-        bool order3 = d == 3;
-        for (const gcp_fed_client& cl : f->clients) order3 = order3 && kernel_order(cl.tensor) == 3;
         if (order3) kern = pick_fed<T, 3>(f->lanes, f->vec);
         else kern = pick_fed<T, 0>(f->lanes, f->vec);
         if (!kern) return set_error(GCP_ERR_UNSUPPORTED, "batched lane shape lanes = %d, vec = %d not built", f->lanes,
                                     f->vec);
         f->client_kernel = reinterpret_cast<const void*>(kern);
-        f->client_lds = std::max(staging + f->lds_bytes, f->bucket_lds);
+        f->client_lds = staging + f->lds_bytes;
         reinterpret_cast<FedArgs<T>*>(f->args)->staging_bytes = (int)staging;
         st = prepare_lds(f->client_kernel, f->client_lds, f->device);
         if (st != GCP_OK) return st;
@@ -527,9 +656,29 @@ template <typename T>
 static gcp_status fed_launch_batched(gcp_fed_s* f, hipStream_t stream)
 {
     const FedArgs<T>& a = *reinterpret_cast<const FedArgs<T>*>(f->args);
-    hipLaunchKernelGGL(reinterpret_cast<FedKernel<T>>(const_cast<void*>(f->client_kernel)),
-                       dim3((unsigned)(f->desc.nclients * f->W)), dim3(f->block), f->client_lds, stream, a);
-    GCP_HIP(hipGetLastError());
+    const unsigned K = (unsigned)f->desc.nclients;
+    if (f->bucketed) {
+        int64_t maxlen = 0;
+        for (const gcp_fed_client& cl : f->clients) maxlen = std::max<int64_t>(maxlen, cl.tensor->rowoff[f->d] * f->desc.R);
+        const unsigned cb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(maxlen, 256), 1024));
+        k_fed_copy<T><<<dim3(cb, K), 256, 0, stream>>>(a);
+        GCP_HIP(hipGetLastError());
+        const unsigned ab = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(f->max_params, 256 * 4), 256));
+        for (int j = 0; j < f->desc.tau; ++j) {
+            hipLaunchKernelGGL(reinterpret_cast<FedStepKernel<T>>(const_cast<void*>(f->sample_kernel)),
+                               dim3((unsigned)f->W, K), dim3(f->block), f->sample_lds, stream, a, j);
+            GCP_HIP(hipGetLastError());
+            hipLaunchKernelGGL(reinterpret_cast<FedKernel<T>>(const_cast<void*>(f->owner_kernel)),
+                               dim3((unsigned)f->nb_max, K), dim3(1024), f->owner_lds, stream, a);
+            GCP_HIP(hipGetLastError());
+            k_fed_adam<T><<<dim3(ab, K), 256, 0, stream>>>(a, j);
+            GCP_HIP(hipGetLastError());
+        }
+    } else {
+        hipLaunchKernelGGL(reinterpret_cast<FedKernel<T>>(const_cast<void*>(f->client_kernel)),
+                           dim3(K * (unsigned)f->W), dim3(f->block), f->client_lds, stream, a);
+        GCP_HIP(hipGetLastError());
+    }
     const int64_t sb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(f->nserver, 256), 2048));
     k_fed_server<T><<<(unsigned)sb, 256, 0, stream>>>(a);
     GCP_HIP(hipGetLastError());
@@ -642,11 +791,18 @@ gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_
         }
     }
     const int esize = f->dt == GCP_F32 ? 4 : 8;
-    f->block = D.block > 0 ? D.block : 256;
+    // row-bucketed batched rounds: on request, or automatically at enough
+    // samples per client step
+    f->want_bucket = D.batched && (D.bucket_modes > 0 || (D.bucket_modes < 0 && D.p + D.q >= kFedBucketMinSamples));
+    f->block = D.block > 0 ? D.block : (f->want_bucket ? 1024 : 256);
     if (f->block % 64 != 0 || f->block > 1024) { delete f; return set_error(GCP_ERR_ARG, "block = %d", f->block); }
-    // lane shape: one column per lane up to R = 64 (coalesced gradient atomics)
-    f->vec = D.vec > 0 ? D.vec : (D.R > 64 && D.R % 2 == 0 ? 2 : 1);
+    // lane shape: one column per lane up to R = 64 (coalesced gradient
+    // atomics); with the row-bucketed scatter, which issues no gradient
+    // atomics for its modes, four columns per lane in FP32
+    const bool wide = f->want_bucket && f->dt == GCP_F32 && D.R % 4 == 0 && D.R <= 64;
+    f->vec = D.vec > 0 ? D.vec : wide ? 4 : (D.R > 64 && D.R % 2 == 0 ? 2 : 1);
     if (D.lanes > 0) f->lanes = D.lanes;
+    else if (wide && D.vec <= 0) f->lanes = D.R <= 32 ? 8 : 16;
     else {
         const int need = (D.R + f->vec - 1) / f->vec;
         f->lanes = 8;

@@ -74,7 +74,7 @@ class FedTile:
     lanes: int = 0
     vec: int = 0
     lds_modes: int = -1
-    bucket_modes: int = 0          # bitmask of row-bucketed modes (0: hardware atomics)
+    bucket_modes: int = -1         # bitmask of row-bucketed modes; -1 automatic, 0 hardware atomics
     bucket_block_samples: int = 0
 
     def key(self):

@@ -126,6 +126,23 @@ def test_fp64_bucketed_blocks_and_workgroups(gpu, tile):
         assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
 
 
+def test_fp64_automatic_bucketing_at_large_sample_counts(gpu):
+    """At >= 2^14 samples per client step the automatic choice is the
+    row-bucketed round (three launches per local step); it still matches the
+    oracle."""
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2613)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2713, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=8192, q=8192, seed=3, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0, cfg, 1, torch.float64)
+    fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, tile=FedTile(lds_modes=0))
+    fed.round(0)
+    fed.status()
+    assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10
+    for cl, oc in zip(fed.clients, ocl):
+        assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
+
+
 @pytest.mark.parametrize("shape", [(32, 1), (16, 2), (8, 4)])
 def test_fp32_batched_equals_plain_and_oracle(gpu, shape):
     gdims, grid, R = [200, 160, 60], (4, 2, 2), 32

@@ -9,8 +9,8 @@ row-bucketed scatter -- against the oracle's gradient on its own samples.
 
 GCP-FedAdam, 64 clients on a 4 x 4 x 4 grid over 20000 x 20000 x 2000 with
 1e5..5e6 nonzeros per client: one batched (graph-replayed) round, with the
-atomic and with the row-bucketed scatter, equals one round of per-client
-launches.
+automatic (row-bucketed at this size) and with the atomic scatter, equals one
+round of per-client launches.
 """
 import sys
 import time
@@ -80,8 +80,7 @@ def test_config5_full_size_batched_equals_plain(gpu):
                     lower=0.0)
     Us = {}
     modes = (("plain", dict(batched=False)), ("graph", dict(batched=True, use_graph=True)),
-             ("graph_bucketed", dict(batched=True, use_graph=True, tile=FedTile(block=1024, lanes=8, vec=4,
-                                                                                  bucket_modes=7))))
+             ("graph_atomic", dict(batched=True, use_graph=True, tile=FedTile(bucket_modes=0))))
     for name, kw in modes:
         fed = FedAdam(clients, gd, U0, cfg, **kw)
         fed.round(0)
@@ -89,7 +88,7 @@ def test_config5_full_size_batched_equals_plain(gpu):
         Us[name] = fed.U.double().cpu().numpy()
         say(f"config 5: {name} round done")
         fed.close()
-    for name in ("graph", "graph_bucketed"):      # atomic and row-bucketed scatter
+    for name in ("graph", "graph_atomic"):      # automatic (row-bucketed here) and atomic scatter
         rel = np.linalg.norm(Us[name] - Us["plain"]) / np.linalg.norm(Us["plain"])
         assert rel <= 1e-5, (name, rel)
     assert np.abs(Us["graph"] - U0.double().cpu().numpy().reshape(-1)).max() > 0     # the round moved U
