@@ -175,7 +175,7 @@ def _median_ms(fn, reps: int, warmup: int) -> float:
     return float(np.median(ts))
 
 
-def run_fedadam(dev, rounds: int):
+def run_fedadam(dev, rounds: int, tune: bool = True):
     """GCP-FedAdam, 64 clients on a 4x4x4 block grid over 20000x20000x2000,
     1e5..5e6 nonzeros per client (log-uniform), rank 32 FP32, tau = 10 local
     steps of 2^16 + 2^16 samples, then the server step: ms per round for
@@ -199,7 +199,7 @@ def run_fedadam(dev, rounds: int):
     plain.status()
     plain.close()
     fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True)
-    tile = autotune.tune_fedadam(fed, rounds=1, warmup=1, use_cache=False)
+    tile = autotune.tune_fedadam(fed, rounds=1, warmup=1, use_cache=False) if tune else fed.tile
     out["batched_tile"] = {"workgroups_per_client": tile.workgroups_per_client, "block": tile.block,
                            "lanes": tile.lanes, "vec": tile.vec, "lds_modes": tile.lds_modes,
                            "bucket_modes": tile.bucket_modes}
@@ -365,7 +365,13 @@ def main():
     ap.add_argument("--hbm-resident", action="store_true",
                     help="only run the HBM-resident-factor experiment (Amazon-shaped tensor) and print its JSON")
     ap.add_argument("--hbm-nnz", type=int, default=500_000_000)
+    ap.add_argument("--fedadam-only", action="store_true",
+                    help="only run the GCP-FedAdam comparison (per-client vs batched round, the library's "
+                         "automatic launch shape, no autotuning) and print its JSON")
     args = ap.parse_args()
+    if args.fedadam_only:
+        print(json.dumps(run_fedadam(torch.device("cuda:0"), args.fed_rounds, tune=False)))
+        return
     if args.hbm_resident:
         out = hbm_resident(torch.device("cuda:0"), args.hbm_nnz, max(1, min(args.steps, 50)), args.warmup)
         print(json.dumps(out))
