@@ -166,15 +166,18 @@ def test_fp32_batched_equals_plain_and_oracle(gpu, shape):
         assert _rel(Ub, Uo) <= 1e-5, mode
 
 
-def test_graph_replays_stay_exact(gpu):
-    """Several graph replays with eager work and synchronisations in between
-    each equal the eager (non-graph) batched rounds."""
+@pytest.mark.parametrize("scatter", ["atomic", "bucketed"])
+def test_graph_replays_stay_exact(gpu, scatter):
+    """Several graph replays (the persistent launch, or the row-bucketed
+    round's three launches per local step) with eager work and
+    synchronisations in between each equal the eager batched rounds."""
     gdims, R = SMALL["gdims"], SMALL["R"]
     blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2612)
     U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2712, dtype=torch.float64)
     cfg = FedConfig(R=R, tau=2, loss="poisson", p=64, q=64, seed=9, lr=1e-2, meta_lr=1e-2, lower=0.0)
-    fg = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=True)
-    fe = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=False)
+    tile = SCATTER[scatter]
+    fg = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=True, tile=tile)
+    fe = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=False, tile=tile)
     for r in range(4):
         fg.round(r)
         fe.round(r)
