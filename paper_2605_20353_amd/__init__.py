@@ -9,4 +9,5 @@ from ._lib import (  # noqa: F401
     gcp_sample, gcp_loss_grad, gcp_adam_step, lib,
 )
 from .autograd import GCPLoss, KruskalModel, gcp_loss  # noqa: F401,E402
-from .fedadam import FedAdam, FedConfig, FedTile  # noqa: F401,E402
+from .fedadam import Batched, FedAdam, FedConfig, FedTile, Plain  # noqa: F401,E402
+from .solver import SolverConfig, SolverResult, gcp_adam  # noqa: F401,E402

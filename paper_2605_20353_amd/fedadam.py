@@ -212,3 +212,22 @@ class FedAdam:
         for b, v in zip(bufs, s):
             b.copy_(v)
         torch.cuda.synchronize()
+
+
+class Batched(FedAdam):
+    """GCP-FedAdam with every client's local steps in shared launches (the
+    persistent launch, or the row-bucketed round's three launches per local
+    step), replayed from a HIP graph by default."""
+
+    def __init__(self, clients, global_dims, U0: torch.Tensor, cfg: FedConfig, use_graph: bool = True,
+                 tile: FedTile | None = None, stream: torch.cuda.Stream | None = None):
+        super().__init__(clients, global_dims, U0, cfg, batched=True, use_graph=use_graph, tile=tile, stream=stream)
+
+
+class Plain(FedAdam):
+    """GCP-FedAdam with one sampled-gradient launch and one Adam launch per
+    client and local step (the per-client reference)."""
+
+    def __init__(self, clients, global_dims, U0: torch.Tensor, cfg: FedConfig,
+                 stream: torch.cuda.Stream | None = None):
+        super().__init__(clients, global_dims, U0, cfg, batched=False, use_graph=False, stream=stream)

@@ -205,6 +205,22 @@ def test_autotuner_keeps_state_and_picks_a_shape(gpu, tmp_path, monkeypatch):
     assert isinstance(tile, FedTile)
 
 
+def test_batched_and_plain_classes_equal_the_flags(gpu):
+    from paper_2605_20353_amd.fedadam import Batched, Plain
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2614)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2714, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=64, q=64, seed=4, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    a = Batched(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg)
+    b = Plain(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg)
+    assert a.batched and a.use_graph and not b.batched
+    a.round(0)
+    b.round(0)
+    a.status()
+    b.status()
+    assert _rel(a.U.cpu().numpy(), b.U.cpu().numpy()) <= 1e-12
+
+
 def test_create_errors(gpu):
     gdims, R = SMALL["gdims"], SMALL["R"]
     blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2614)
