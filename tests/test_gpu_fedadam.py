@@ -205,6 +205,24 @@ def test_autotuner_keeps_state_and_picks_a_shape(gpu, tmp_path, monkeypatch):
     assert isinstance(tile, FedTile)
 
 
+@pytest.mark.parametrize("scatter", ["atomic", "bucketed"])
+def test_fp64_four_way_rounds_match_oracle(gpu, scatter):
+    """4-way client blocks: the general-order kernels of both batched forms."""
+    gdims, R = [20, 18, 12, 8], 3
+    blocks = _blocks(gdims, (2, 2, 1, 2), R, 30, 120, seed=2615)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2715, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=200, q=150, seed=6, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    tile = FedTile() if scatter == "atomic" else FedTile(lds_modes=0, bucket_modes=15, bucket_block_samples=512)
+    fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, tile=tile)
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0, cfg, 2, torch.float64)
+    assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10
+    for cl, oc in zip(fed.clients, ocl):
+        assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
+
+
 def test_batched_and_plain_classes_equal_the_flags(gpu):
     from paper_2605_20353_amd.fedadam import Batched, Plain
     gdims, R = SMALL["gdims"], SMALL["R"]
