@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the GCP-FedAdam round and autograd measurements")
     ap.add_argument("--fed-rounds", type=int, default=5)
