@@ -192,6 +192,19 @@ constexpr int samples_in_flight()
     return U;
 }
 
+// Entries in flight per lane group in the owner pass of the bucketed scatter
+// (float, four columns per lane: GCP_OWNER_UNROLL_WIDE).
+#ifndef GCP_OWNER_UNROLL_WIDE
+#define GCP_OWNER_UNROLL_WIDE GCP_UNROLL_WIDE
+#endif
+template <typename T, int D, int LANES, int VEC>
+constexpr int owner_in_flight()
+{
+    constexpr int U = (D == 0 || LANES < 4) ? 1 : sizeof(T) == 8 ? 2 : VEC == 4 ? GCP_OWNER_UNROLL_WIDE : 4;
+    static_assert(U >= 1 && LANES % U == 0, "entries in flight must divide the lanes per entry");
+    return U;
+}
+
 // One chunk of 64 samples: phase 1 (one lane per sample: draw or read the
 // sample, stage it in the wave's LDS slice) and phase 2 (LANES lanes per
 // sample: gather rows, model value, loss derivative, scatter).  Shared by the
@@ -396,7 +409,7 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
                                                   int64_t j0, int64_t j1, T* part, int* seg_cnt)
 {
     constexpr int S = 64 / LANES;
-    constexpr int U = samples_in_flight<T, D, LANES, VEC>();
+    constexpr int U = owner_in_flight<T, D, LANES, VEC>();
     constexpr int DM = D > 0 ? D : kMaxModes;
     static_assert(VEC == 1 || VEC == 2 || VEC == 4, "columns per lane");
     const int nwaves = blockDim.x >> 6;
@@ -425,6 +438,86 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
     }
     __syncthreads();
 
+    if constexpr (D > 0) {
+        // Bit-packed keys: every load below is unconditional.  The D - 1 modes
+        // other than k are enumerated at compile time (shift, mask, row offset
+        // picked with compile-time indices), lanes past column R read column 0
+        // and lanes past the segment's end re-read its last entry, so each load
+        // has an in-bounds address and no branch around it.  Loads under a
+        // branch make the compiler wait for all outstanding loads before each
+        // one, which serialises the gathers of a pass.
+        static_assert(D >= 2, "orders with their own kernels");
+        constexpr int DO = D - 1;
+        int sh_o[DO];
+        uint32_t mk_o[DO], ro_o[DO];
+#pragma unroll
+        for (int o = 0; o < DO; ++o) {
+            const int m = o + (o >= k ? 1 : 0);
+            sh_o[o] = 0;
+            mk_o[o] = 0;
+            ro_o[o] = 0;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk)
+                if (kk == m) {
+                    sh_o[o] = P.sc.L.shift[kk];
+                    mk_o[o] = (uint32_t)P.sc.L.mask[kk];
+                    ro_o[o] = (uint32_t)P.rowoff[kk];
+                }
+        }
+        const int colL = col_ok ? col0 : 0;
+        for (int64_t j = j0 + wave; j < j1; j += nwaves) {
+            const int cnt = seg_cnt[j - j0];
+            if (cnt == 0) continue;
+            const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
+            uint4 nxt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) nxt[u] = seg[min(u * S + g, cnt - 1)];
+            for (int base = 0; base < cnt; base += S * U) {
+                uint64_t key[U];
+                T y[U];
+                T a[U][DO][VEC];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    key[u] = (uint64_t)nxt[u].x | ((uint64_t)nxt[u].y << 32);
+                    y[u] = entry_y<T>(nxt[u]);
+#pragma unroll
+                    for (int o = 0; o < DO; ++o) {
+                        const uint32_t row = ro_o[o] + ((uint32_t)(key[u] >> sh_o[o]) & mk_o[o]);
+                        load_cols<T, VEC>(P.A + row_elem(row, R) + colL, a[u][o]);
+                    }
+                }
+                // the next pass's entries stay in flight through this pass's
+                // scatter
+#pragma unroll
+                for (int u = 0; u < U; ++u) nxt[u] = seg[min(base + S * U + u * S + g, cnt - 1)];
+                // keeps the gathers here: sunk into the scatter branch below
+                // they would issue after the prefetch, and waiting for them
+                // would wait for the prefetch as well
+                __asm__ volatile("" ::: "memory");
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (base + u * S + g >= cnt || !col_ok) continue;
+                    const uint32_t i = (uint32_t)((key[u] >> shift_k) & mask_k) - (uint32_t)r0;
+                    T c[VEC];
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        c[v] = y[u];
+#pragma unroll
+                        for (int o = 0; o < DO; ++o) c[v] *= a[u][o][v];
+                    }
+                    T* dst = part + i * (uint32_t)R + col0;
+                    lds_add(dst, c[0]);
+                    if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
+                    if constexpr (VEC > 2) {
+                        lds_add(dst + 2, c[2]);
+                        lds_add(dst + 3, c[3]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        return;
+    }
     for (int64_t j = j0 + wave; j < j1; j += nwaves) {
         const int cnt = seg_cnt[j - j0];
         const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
