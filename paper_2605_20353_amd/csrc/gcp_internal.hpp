@@ -269,15 +269,27 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t k)
     return k;
 }
 
+typedef unsigned long long u64x2_vec __attribute__((ext_vector_type(2)));
+
+// Linear-probing membership test.  Each probe is one 16-byte load of the
+// aligned slot pair holding the current slot, scanned from that slot on, so a
+// lookup whose home slot is even and occupied can still end on its first
+// load.  The table is an allocation of its own with at least 2^10 slots, so a
+// pair never runs past its end.
 __device__ __forceinline__ bool table_contains(const uint64_t* __restrict__ table, uint64_t mask, int log2n,
                                                uint64_t key)
 {
     uint64_t h = log2n > 0 ? (mix64(key) >> (64 - log2n)) : 0;
     for (;;) {
-        uint64_t v = __builtin_nontemporal_load(table + h);
-        if (v == key) return true;
-        if (v == kEmptySlot) return false;
-        h = (h + 1) & mask;
+        const uint64_t pair = h & ~uint64_t(1);
+        const u64x2_vec t = __builtin_nontemporal_load(reinterpret_cast<const u64x2_vec*>(table + pair));
+        if ((h & 1) == 0) {
+            if (t.x == key) return true;
+            if (t.x == kEmptySlot) return false;
+        }
+        if (t.y == key) return true;
+        if (t.y == kEmptySlot) return false;
+        h = (pair + 2) & mask;
     }
 }
 
