@@ -169,7 +169,8 @@ int64_t gcp_struct_size(const char* name);
  * GCP_ERR_UNSUPPORTED).  coords_dev: device int64 [nnz x d]; vals_dev:
  * device values of dtype dt.  Copies and packs the nonzeros into 16-byte
  * device records and builds an open-addressing hash table of the packed
- * coordinates (the O(1) membership search of Sec. 3.1.1).  The inputs may be
+ * coordinates (the O(1) membership search of Sec. 3.1.1; the smallest power
+ * of two >= 4 nnz slots of 8 bytes, at least 2^10).  The inputs may be
  * freed after the call returns.  Synchronises the stream: repeated or
  * out-of-range coordinates return GCP_ERR_DATA.  The handle owns its device
  * memory until gcp_tensor_destroy. */
