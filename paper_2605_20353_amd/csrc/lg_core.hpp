@@ -98,6 +98,23 @@ __device__ __forceinline__ void lds_add(float* p, float v)
     }
 }
 
+// Two adjacent floats (8-byte aligned) added by one 64-bit compare-and-swap
+// loop: half the serial LDS round trips of two single adds.
+__device__ __forceinline__ void lds_add2(float* p, float a, float b)
+{
+    unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
+    unsigned long long old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const float lo = __uint_as_float((unsigned)old) + a;
+        const float hi = __uint_as_float((unsigned)(old >> 32)) + b;
+        const unsigned long long nv = (unsigned long long)__float_as_uint(lo) |
+                                      ((unsigned long long)__float_as_uint(hi) << 32);
+        if (__hip_atomic_compare_exchange_strong(u, &old, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            break;
+    }
+}
+
 __device__ __forceinline__ void lds_add(double* p, double v)
 {
     unsigned long long* u = reinterpret_cast<unsigned long long*>(p);
@@ -506,11 +523,17 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
                         for (int o = 0; o < DO; ++o) c[v] *= a[u][o][v];
                     }
                     T* dst = part + i * (uint32_t)R + col0;
-                    lds_add(dst, c[0]);
-                    if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
-                    if constexpr (VEC > 2) {
-                        lds_add(dst + 2, c[2]);
-                        lds_add(dst + 3, c[3]);
+                    if constexpr (sizeof(T) == 4 && VEC >= 2) {
+                        // dst is 8-byte aligned: R and col0 are multiples of VEC
+                        lds_add2(dst, c[0], c[1]);
+                        if constexpr (VEC > 2) lds_add2(dst + 2, c[2], c[3]);
+                    } else {
+                        lds_add(dst, c[0]);
+                        if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
+                        if constexpr (VEC > 2) {
+                            lds_add(dst + 2, c[2]);
+                            lds_add(dst + 3, c[3]);
+                        }
                     }
                 }
             }
