@@ -128,6 +128,26 @@ __device__ __forceinline__ void lds_add(double* p, double v)
     }
 }
 
+// Adds VEC consecutive columns to LDS; float column pairs (8-byte aligned:
+// row strides and column offsets are multiples of VEC) go through one 64-bit
+// compare-and-swap each.
+template <typename T, int VEC>
+__device__ __forceinline__ void lds_add_cols(T* dst, const T (&c)[VEC])
+{
+    static_assert(VEC == 1 || VEC == 2 || VEC == 4, "columns per lane");
+    if constexpr (sizeof(T) == 4 && VEC >= 2) {
+        lds_add2(dst, c[0], c[1]);
+        if constexpr (VEC == 4) lds_add2(dst + 2, c[2], c[3]);
+    } else {
+        lds_add(dst, c[0]);
+        if constexpr (VEC >= 2) lds_add(dst + 1, c[1]);
+        if constexpr (VEC == 4) {
+            lds_add(dst + 2, c[2]);
+            lds_add(dst + 3, c[3]);
+        }
+    }
+}
+
 // Element offset of column 0 of model row `row` (row < 2^32, checked when the
 // tensor is created): one 32 x 32 -> 64-bit multiply.
 __device__ __forceinline__ uint64_t row_elem(uint64_t row, int R)
@@ -339,27 +359,28 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
             // rather than holding them live across the gathers
             uint32_t ci[DM];
             unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
+            // per mode not bucketed: the leave-one-out product y prod_{n != k}
+            // A_n[i_n, :], added to the LDS-private copy (column pairs) or to G
+            // by global atomics
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                // leave-one-out products by prefix and suffix running products
-                T pre[DM];
-                pre[0] = y;
+            for (int k = DM - 1; k >= 0; --k) {
+                if (k < dd && !((P.bucket_mask >> k) & 1u)) {
+                    T c[VEC];
 #pragma unroll
-                for (int k = 1; k < DM; ++k)
-                    if (k < dd) pre[k] = pre[k - 1] * a[u][k - 1][v];
-                T suf = T(1);
+                    for (int v = 0; v < VEC; ++v) {
+                        T pre = y;
 #pragma unroll
-                for (int k = DM - 1; k >= 0; --k) {
-                    if (k < dd) {
-                        const T c = pre[k] * suf;
-                        suf *= a[u][k][v];
-                        if ((P.bucket_mask >> k) & 1u) continue;
-                        const uint32_t i = ci[k];
-                        if ((P.lds_mask >> k) & 1u) {
-                            lds_add(priv + P.lds_off[k] + i * (uint32_t)R + col0 + v, c);
-                        } else {
-                            global_add(P.G + row_elem((uint64_t)P.rowoff[k] + i, R) + col0 + v, c);
-                        }
+                        for (int kk = 0; kk < DM; ++kk)
+                            if (kk < dd && kk != k) pre *= a[u][kk][v];
+                        c[v] = pre;
+                    }
+                    const uint32_t i = ci[k];
+                    if ((P.lds_mask >> k) & 1u) {
+                        lds_add_cols<T, VEC>(priv + P.lds_off[k] + i * (uint32_t)R + col0, c);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v)
+                            global_add(P.G + row_elem((uint64_t)P.rowoff[k] + i, R) + col0 + v, c[v]);
                     }
                 }
             }
@@ -522,19 +543,7 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
 #pragma unroll
                         for (int o = 0; o < DO; ++o) c[v] *= a[u][o][v];
                     }
-                    T* dst = part + i * (uint32_t)R + col0;
-                    if constexpr (sizeof(T) == 4 && VEC >= 2) {
-                        // dst is 8-byte aligned: R and col0 are multiples of VEC
-                        lds_add2(dst, c[0], c[1]);
-                        if constexpr (VEC > 2) lds_add2(dst + 2, c[2], c[3]);
-                    } else {
-                        lds_add(dst, c[0]);
-                        if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
-                        if constexpr (VEC > 2) {
-                            lds_add(dst + 2, c[2]);
-                            lds_add(dst + 3, c[3]);
-                        }
-                    }
+                    lds_add_cols<T, VEC>(part + i * (uint32_t)R + col0, c);
                 }
             }
         }
@@ -595,13 +604,7 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
                     for (int kk = 0; kk < DM; ++kk)
                         if (kk < dd) c[v] *= a[u][kk][v];
                 }
-                T* dst = part + i * (uint32_t)R + col0;
-                lds_add(dst, c[0]);
-                if constexpr (VEC > 1) lds_add(dst + 1, c[1]);
-                if constexpr (VEC > 2) {
-                    lds_add(dst + 2, c[2]);
-                    lds_add(dst + 3, c[3]);
-                }
+                lds_add_cols<T, VEC>(part + i * (uint32_t)R + col0, c);
             }
         }
     }
