@@ -256,6 +256,31 @@ BUCKET_TILES = [
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", ["r32", "r64_4way"])
+def test_bucketed_scatter_every_lane_shape(gpu, dtype, name):
+    """The owner pass adds 1, 2 or 4 columns per lane (float column pairs by
+    one 64-bit compare-and-swap): every lane shape, bucketed alone and with
+    the LDS-private strategy on one mode, against the oracle."""
+    t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
+    pq = (20000, 9001)
+    t_gpu.reserve(sum(pq), R)
+    A = model(dims, R, dtype, gpu)
+    sp = G.SampleParams("stratified", pq[0], pq[1], seed=37, step=4)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    every = (1 << len(dims)) - 1
+    for lanes, vec in _shapes(R, dtype):
+        for lds in (0, 1):
+            tl = dict(lanes=lanes, vec=vec, bucket_modes=every & ~lds, lds_modes=lds, bucket_block_samples=1024,
+                      bucket_splits=2, bucket_block=256)
+            say(f"bucketed shape {name} {dtype} {tl}")
+            Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(**tl))
+            t_gpu.status()
+            err = split_rel_err(Gg.double().cpu().numpy(), Go, dims, R)
+            assert err <= TOL[dtype], (tl, err)
+            assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("loss", ["poisson", "gaussian"])
 @pytest.mark.parametrize("pq", [(70000, 50001), (3000, 2000)])
 def test_bucketed_scatter_matches_oracle(gpu, dtype, loss, pq):
