@@ -354,33 +354,70 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                 bkey[s - block_s0] = key[u];
                 by[s - block_s0] = y;
             }
-            if (!col_ok) continue;
+            // all modes bucketed: the owner pass forms the products
+            if (!col_ok || P.bucket_mask == (1u << dd) - 1) continue;
             // coordinates again from the key (a few shifts when bit-packed),
             // rather than holding them live across the gathers
             uint32_t ci[DM];
             unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
-            // per mode not bucketed: the leave-one-out product y prod_{n != k}
-            // A_n[i_n, :], added to the LDS-private copy (column pairs) or to G
-            // by global atomics
+            if constexpr (sizeof(T) == 4 && VEC >= 2) {
+                // leave-one-out products y prod_{n != k} A_n[i_n, :] by prefix
+                // and suffix running products, then per mode not bucketed:
+                // added to the LDS-private copy (column pairs) or to G by
+                // global atomics
+                T cv[DM][VEC];
 #pragma unroll
-            for (int k = DM - 1; k >= 0; --k) {
-                if (k < dd && !((P.bucket_mask >> k) & 1u)) {
-                    T c[VEC];
+                for (int v = 0; v < VEC; ++v) {
+                    T pre[DM];
+                    pre[0] = y;
 #pragma unroll
-                    for (int v = 0; v < VEC; ++v) {
-                        T pre = y;
+                    for (int k = 1; k < DM; ++k)
+                        if (k < dd) pre[k] = pre[k - 1] * a[u][k - 1][v];
+                    T suf = T(1);
 #pragma unroll
-                        for (int kk = 0; kk < DM; ++kk)
-                            if (kk < dd && kk != k) pre *= a[u][kk][v];
-                        c[v] = pre;
+                    for (int k = DM - 1; k >= 0; --k) {
+                        if (k < dd) {
+                            cv[k][v] = pre[k] * suf;
+                            suf *= a[u][k][v];
+                        }
                     }
-                    const uint32_t i = ci[k];
-                    if ((P.lds_mask >> k) & 1u) {
-                        lds_add_cols<T, VEC>(priv + P.lds_off[k] + i * (uint32_t)R + col0, c);
-                    } else {
+                }
 #pragma unroll
-                        for (int v = 0; v < VEC; ++v)
-                            global_add(P.G + row_elem((uint64_t)P.rowoff[k] + i, R) + col0 + v, c[v]);
+                for (int k = DM - 1; k >= 0; --k) {
+                    if (k < dd && !((P.bucket_mask >> k) & 1u)) {
+                        const uint32_t i = ci[k];
+                        if ((P.lds_mask >> k) & 1u) {
+                            lds_add_cols<T, VEC>(priv + P.lds_off[k] + i * (uint32_t)R + col0, cv[k]);
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < VEC; ++v)
+                                global_add(P.G + row_elem((uint64_t)P.rowoff[k] + i, R) + col0 + v, cv[k][v]);
+                        }
+                    }
+                }
+            } else {
+                // no column pairs: each product goes out as soon as it is formed
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    T pre[DM];
+                    pre[0] = y;
+#pragma unroll
+                    for (int k = 1; k < DM; ++k)
+                        if (k < dd) pre[k] = pre[k - 1] * a[u][k - 1][v];
+                    T suf = T(1);
+#pragma unroll
+                    for (int k = DM - 1; k >= 0; --k) {
+                        if (k < dd) {
+                            const T c = pre[k] * suf;
+                            suf *= a[u][k][v];
+                            if ((P.bucket_mask >> k) & 1u) continue;
+                            const uint32_t i = ci[k];
+                            if ((P.lds_mask >> k) & 1u) {
+                                lds_add(priv + P.lds_off[k] + i * (uint32_t)R + col0 + v, c);
+                            } else {
+                                global_add(P.G + row_elem((uint64_t)P.rowoff[k] + i, R) + col0 + v, c);
+                            }
+                        }
                     }
                 }
             }
