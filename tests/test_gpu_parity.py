@@ -96,6 +96,38 @@ def test_samples_bit_exact(gpu, dtype, name, pq):
     np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_samples_bit_exact_mostly_full_tensor(gpu, dtype):
+    """7 of every 8 cells are nonzeros: most zero-sample attempts land on a
+    stored nonzero, so the membership probe (slot pairs, scanning on past a
+    pair) and the redraw loop run for nearly every zero sample.  Draws and
+    the sampled gradient on them equal the oracle's."""
+    dims = [20, 20, 20]
+    rng = np.random.default_rng(2611)
+    cells = rng.permutation(8000)[:7000]
+    coords = np.stack(np.unravel_index(cells, dims), axis=1).astype(np.int64)
+    vals = rng.integers(1, 6, size=7000).astype(np.float64)
+    t_gpu = G.SparseTensor(dims, torch.from_numpy(coords).to(gpu), torch.from_numpy(vals).to(dtype).to(gpu))
+    t_ora = oracle.SparseTensor(dims, coords, vals)
+    p, q = 3000, 5000
+    say(f"mostly-full sample {dtype}")
+    sp = G.SampleParams("stratified", p, q, seed=7, step=5, client=1, max_attempts=400)
+    c, x, w = G.gcp_sample(t_gpu, sp)
+    t_gpu.status()
+    oc, ox, ow = oracle.sample_stratified(t_ora, p, q, 7, 5, 1, max_attempts=400)
+    np.testing.assert_array_equal(c.cpu().numpy(), oc)
+    np.testing.assert_array_equal(x.cpu().numpy(), ox.astype(x.cpu().numpy().dtype))
+    np.testing.assert_array_equal(w.cpu().numpy(), ow.astype(w.cpu().numpy().dtype))
+    assert not np.isin(np.ravel_multi_index(oc[p:].T, dims), cells).any()
+    R = 8
+    A = model(dims, R, dtype, gpu)
+    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson")
+    t_gpu.status()
+    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+    assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
 def test_samples_depend_on_step_seed_client(gpu):
     t_gpu, _, _, _ = make_case("cfg1_50x40x30", torch.float64, gpu)
     base = G.gcp_sample(t_gpu, G.SampleParams("stratified", 100, 100, seed=1, step=0, client=0))[0]
