@@ -134,8 +134,8 @@ def tune_fedadam(fed: FedAdam, candidates=None, rounds: int = 1, warmup: int = 1
 def loss_grad_candidates(R: int, dtype, reserved: bool):
     """The library's automatic choice, then the atomic scatter with one
     column per lane, then (with a reserved workspace) the row-bucketed
-    scatter over a few lane shapes, workgroup sizes, owner-pass workgroup
-    sizes and splits."""
+    scatter over a few lane shapes, workgroup sizes, samples per sorting
+    workgroup, owner-pass workgroup sizes and splits."""
     out = [G.Tile()]
     out.append(G.Tile(lds_modes=0, bucket_modes=0))
     if reserved:
@@ -153,6 +153,11 @@ def loss_grad_candidates(R: int, dtype, reserved: bool):
                 for bblock, splits in ((1024, 0), (1024, 16), (1024, 32), (512, 0), (512, 32)):
                     out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=-1, bucket_modes=-1,
                                       bucket_splits=splits, bucket_block=bblock))
+            # larger sorting workgroups: fewer, longer segments per row block
+            for block in (512, 1024):
+                for splits in (0, 16):
+                    out.append(G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=-1, bucket_modes=-1,
+                                      bucket_block_samples=4096, bucket_splits=splits, bucket_block=1024))
     return out
 
 

@@ -284,6 +284,7 @@ BUCKET_TILES = [
     dict(bucket_modes=7, lds_modes=0, bucket_block_samples=512, bucket_splits=7, bucket_block=192),
     dict(bucket_modes=7, lds_modes=2, bucket_block_samples=4096, bucket_block=1024),
     dict(bucket_modes=7, lds_modes=0, bucket_block_samples=8192, bucket_lds_bytes=65536),
+    dict(block=1024, bucket_modes=-1, bucket_block_samples=4096, bucket_splits=16, bucket_block=1024),
 ]
 
 
