@@ -90,6 +90,9 @@ def lib():
         L.ora_loss_grad.argtypes = [C.c_int, i64p, C.c_int, f64p, C.c_int64, i64p, f64p, f64p,
                                     C.c_int, C.c_int64, f64p, f64p]
         L.ora_loss_grad.restype = None
+        L.ora_loss_grad_bound.argtypes = [C.c_int, i64p, C.c_int, f64p, C.c_int64, i64p, f64p, f64p,
+                                          C.c_int, C.c_int64, C.c_double, f64p, f64p, i64p]
+        L.ora_loss_grad_bound.restype = None
         L.ora_adam.argtypes = [C.c_int64, f64p, f64p, f64p, f64p, C.c_int64, C.c_double,
                                C.c_double, C.c_double, C.c_double, C.c_double]
         L.ora_adam.restype = None
@@ -239,6 +242,49 @@ def loss_grad(dims, R: int, A, coords, x, w, loss, n_semi: int = 0):
                         _p(coords, C.c_int64), _p(x, C.c_double), _p(w, C.c_double),
                         _loss_id(loss), int(n_semi), _p(G, C.c_double), C.byref(F))
     return G, float(F.value)
+
+
+U_F32 = 2.0 ** -24      # unit roundoff of binary32
+U_F64 = 2.0 ** -53      # unit roundoff of binary64
+
+
+def loss_grad_bound_parts(dims, R: int, A, coords, x, w, loss, u: float, n_semi: int = 0):
+    """Per-element ingredients of the rounding-error bound of a sampled
+    gradient computed with unit roundoff u in any summation order (see
+    ora_loss_grad_bound): (abssum, yerr) shaped like A and count per model
+    row."""
+    dims = _i64(dims)
+    A = _f64(A).reshape(-1)
+    coords = _i64(coords).reshape(-1, int(dims.size))
+    x = _f64(x)
+    w = _f64(w)
+    n = int(coords.shape[0])
+    rows = int(dims.sum())
+    abssum = np.zeros(rows * R)
+    yerr = np.zeros(rows * R)
+    count = np.zeros(rows, dtype=np.int64)
+    lib().ora_loss_grad_bound(int(dims.size), _p(dims, C.c_int64), R, _p(A, C.c_double), n,
+                              _p(coords, C.c_int64), _p(x, C.c_double), _p(w, C.c_double),
+                              _loss_id(loss), int(n_semi), float(u), _p(abssum, C.c_double),
+                              _p(yerr, C.c_double), _p(count, C.c_int64))
+    return abssum, yerr, count
+
+
+def _gamma(n, u):
+    n = np.asarray(n, dtype=np.float64)
+    return n * u / (1.0 - n * u)
+
+
+def grad_error_bound(dims, R: int, A, coords, x, w, loss, u: float, n_semi: int = 0) -> np.ndarray:
+    """First-order bound, per gradient element, on |G^ - G| for a sampled
+    gradient G^ computed with unit roundoff u (any order of the additions)
+    against the exact gradient G of the same samples and factors:
+    yerr + (gamma_d + gamma_{count-1}) abssum."""
+    dims = _i64(dims)
+    abssum, yerr, count = loss_grad_bound_parts(dims, R, A, coords, x, w, loss, u, n_semi)
+    d = int(dims.size)
+    depth = np.repeat(np.maximum(count - 1, 0), R)
+    return yerr + (_gamma(d, u) + _gamma(depth, u)) * abssum
 
 
 def adam(A: np.ndarray, G, B: np.ndarray, C_: np.ndarray, t: int, lr: float = 1e-3,

@@ -352,6 +352,115 @@ void ora_loss_grad(int d, const int64_t* dims, int R, const double* A, int64_t n
 }
 
 /* ------------------------------------------------------------------------ */
+/* Rounding-error bound of a sampled gradient computed in a floating-point   */
+/* format with unit roundoff u (2^-24 for binary32, 2^-53 for binary64),     */
+/* element by element, for ANY order of its sums (lane-parallel model        */
+/* values, atomics, per-workgroup partial sums), against the exact gradient  */
+/* of the same samples and factors.  It rests on the standard model          */
+/* fl(a op b) = (a op b)(1 + t), |t| <= u, and gamma_n = n u / (1 - n u)      */
+/* (Higham, "Accuracy and Stability of Numerical Algorithms", 2nd ed.,       */
+/* Sec. 2.2 and 3.1): a product of n + 1 factors has relative error at most  */
+/* gamma_n, and a sum of terms added in any tree of depth n has absolute     */
+/* error at most gamma_n times the sum of their magnitudes.                  */
+/*                                                                          */
+/* Per sample s, with P_r = prod_k |A_k[i_k, r]| and mabs = sum_r P_r:        */
+/*   |m^ - m| <= dm = gamma_{d+R} mabs            (d - 1 products, R terms)   */
+/*   |f'^ - f'| <= e_f  from dm and the rounding of f' itself (per loss       */
+/*                     below; exp is allowed 4u, a correctly rounded         */
+/*                     division u),                                          */
+/*   |y^ - y| <= e_y = |w| e_f + 3u |w| (|f'| + e_f)   (w rounded to the      */
+/*                     format, one product, the device scale factor),        */
+/* and for every mode k and column r, with Q = prod_{n != k} |A_n[i_n, r]|:   */
+/*   yerr[k, i_k, r]   += e_y Q                                              */
+/*   abssum[k, i_k, r] += |y| Q                                              */
+/*   count[k, i_k]     += 1.                                                 */
+/* The caller combines them as                                               */
+/*   |G^ - G| <= yerr + (gamma_d + gamma_{count - 1}) abssum                 */
+/* (d multiplications per contribution, count - 1 additions in any order).   */
+/* Samples s < n_semi are semi-stratified nonzeros with y = w (f'(x, m) -    */
+/* f'(0, m)).  A bound is +inf where a loss is not Lipschitz enough near m   */
+/* for the estimate to hold (a Poisson m + eps within dm of zero).           */
+/* ------------------------------------------------------------------------ */
+
+static double ora_gamma(double n, double u)
+{
+    return n * u / (1.0 - n * u);
+}
+
+/* Bound on |f'^(x, m^) - f'(x, m)| given |m^ - m| <= dm. */
+static double ora_df_err(int loss, double x, double m, double dm, double u)
+{
+    switch (loss) {
+    case ORA_LOSS_GAUSSIAN: {             /* fl(m^ - x) */
+        double df = m - x;
+        return dm + u * (fabs(df) + dm);
+    }
+    case ORA_LOSS_POISSON: {              /* fl(1 - fl(x / fl(m^ + eps))) */
+        double den = m + ORA_POISSON_EPS;
+        double eden = dm + u * (fabs(den) + dm);
+        if (eden >= 0.5 * fabs(den)) return INFINITY;
+        double q = x / den;
+        double eq = fabs(q) * eden / (fabs(den) - eden) + u * fabs(q) * fabs(den) / (fabs(den) - eden);
+        return eq + u * (fabs(1.0 - q) + eq);
+    }
+    case ORA_LOSS_BERNOULLI_LOGIT: {      /* sigmoid(m^) - x, sigmoid via exp */
+        double sig;
+        if (m >= 0) sig = 1.0 / (1.0 + exp(-m));
+        else { double e = exp(m); sig = e / (1.0 + e); }
+        double es = 0.25 * dm + 6.0 * u * sig;
+        return es + u * (fabs(sig - x) + es);
+    }
+    default: return INFINITY;
+    }
+}
+
+void ora_loss_grad_bound(int d, const int64_t* dims, int R, const double* A, int64_t n,
+                         const int64_t* coords, const double* x, const double* w, int loss,
+                         int64_t n_semi, double u, double* abssum, double* yerr, int64_t* count)
+{
+    int64_t rowoff[9];
+    ora_rowoff(d, dims, rowoff);
+    memset(abssum, 0, sizeof(double) * (size_t)(rowoff[d] * R));
+    memset(yerr, 0, sizeof(double) * (size_t)(rowoff[d] * R));
+    memset(count, 0, sizeof(int64_t) * (size_t)rowoff[d]);
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t* idx = coords + s * d;
+        double m = ora_model_value(d, dims, R, A, idx);
+        double mabs = 0.0;
+        for (int r = 0; r < R; ++r) {
+            double prod = 1.0;
+            for (int k = 0; k < d; ++k) prod *= fabs(A[(rowoff[k] + idx[k]) * R + r]);
+            mabs += prod;
+        }
+        double dm = ora_gamma((double)(d + R), u) * mabs;
+        double aw = fabs(w[s]);
+        double y, ey;
+        if (s < n_semi) {
+            double d1 = ora_df(loss, x[s], m), d0 = ora_df(loss, 0.0, m);
+            double e1 = ora_df_err(loss, x[s], m, dm, u), e0 = ora_df_err(loss, 0.0, m, dm, u);
+            y = w[s] * (d1 - d0);
+            ey = aw * (e1 + e0) + 3.0 * u * aw * (fabs(d1) + e1 + fabs(d0) + e0) + 2.0 * u * fabs(y);
+        } else {
+            double df = ora_df(loss, x[s], m);
+            double ef = ora_df_err(loss, x[s], m, dm, u);
+            y = w[s] * df;
+            ey = aw * ef + 3.0 * u * aw * (fabs(df) + ef);
+        }
+        for (int k = 0; k < d; ++k) {
+            const int64_t row = rowoff[k] + idx[k];
+            count[row] += 1;
+            for (int r = 0; r < R; ++r) {
+                double q = 1.0;
+                for (int nn = 0; nn < d; ++nn)
+                    if (nn != k) q *= fabs(A[(rowoff[nn] + idx[nn]) * R + r]);
+                abssum[row * R + r] += fabs(y) * q;
+                yerr[row * R + r] += ey * q;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Adam update (Alg. adam-update), over the one contiguous parameter vector  */
 /* (Sec. 3.1.3).  t >= 1 counts the updates of this model; epsilon sits      */
 /* inside the square root as the paper writes it; l is the lower bound.     */
