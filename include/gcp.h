@@ -227,6 +227,31 @@ gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, const gcp_sa
                          const void* scale_dev, void* G_out, double* loss_out,
                          const gcp_tile* tile, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as gcp_loss_grad, with the same arguments, results and errors, except
+ * that the row-bucketed scatter uses the library's own fixed scratch region of
+ * gcp_noalloc_scratch_bytes() bytes (128 MiB) per GPU instead of the
+ * handle's gcp_tensor_reserve workspace, and no call allocates or frees device
+ * memory.  A call needs nblocks * spb * b * 16 + nbk * nblocks * 8 bytes of it
+ * (spb samples per sorting workgroup, nblocks = ceil((p + q) / spb), b
+ * bucketed modes, nbk row blocks over those modes); that is 97 MiB for 2^21
+ * samples of a 10000 x 8000 x 6000 tensor at rank 32 in float32.  With
+ * tile->bucket_modes = -1 (automatic) a call whose need exceeds the scratch
+ * uses hardware atomics instead; an explicit bucket_modes request that does
+ * not fit returns GCP_ERR_ARG.  The first call on a device looks up the
+ * scratch region's address there; each GPU keeps its copy until the process
+ * ends.  All calls on one GPU share its copy: calls that overlap in time on
+ * one GPU (different streams, or different host threads without ordering)
+ * race and give wrong gradients; calls ordered on one stream are safe. */
+gcp_status gcp_loss_grad_noalloc(gcp_tensor t, const gcp_sample_params* sp, const gcp_samples* smp,
+                                 const void* A, int R, gcp_loss loss, unsigned flags,
+                                 const void* scale_dev, void* G_out, double* loss_out,
+                                 const gcp_tile* tile, hipStream_t stream);
+
+/* Size in bytes of the per-GPU scratch region of gcp_loss_grad_noalloc. */
+int64_t gcp_noalloc_scratch_bytes(void);
+
 /* Alg. adam-update on n contiguous parameters of dtype dt, one launch:
  *   B = b1 B + (1-b1) G;  C = b2 C + (1-b2) G*G;
  *   A = max(A - lr (B/(1-b1^t)) / sqrt(C/(1-b2^t) + eps), lower)

@@ -81,6 +81,9 @@ def _declare(L):
         "gcp_sample": ([vp, C.POINTER(gcp_sample_params), vp, vp, vp, vp], C.c_int),
         "gcp_loss_grad": ([vp, C.POINTER(gcp_sample_params), C.POINTER(gcp_samples), vp, C.c_int, C.c_int,
                            u, vp, vp, vp, C.POINTER(gcp_tile), vp], C.c_int),
+        "gcp_loss_grad_noalloc": ([vp, C.POINTER(gcp_sample_params), C.POINTER(gcp_samples), vp, C.c_int,
+                                   C.c_int, u, vp, vp, vp, C.POINTER(gcp_tile), vp], C.c_int),
+        "gcp_noalloc_scratch_bytes": ([], i64),
         "gcp_adam_step": ([vp, vp, vp, vp, i64, C.c_int, i64, d_, d_, d_, d_, d_, u, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -304,9 +307,12 @@ def gcp_loss_grad(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, lo
                   G: torch.Tensor | None = None, loss_out: torch.Tensor | None = None,
                   samples=None, loss_only: bool = False, accumulate: bool = False,
                   scale: torch.Tensor | None = None, tile: Tile | None = None, want_loss: bool = True,
-                  stream=None):
+                  stream=None, noalloc: bool = False):
     """Fused sampled objective and gradient.  Returns (G, loss_out) where
-    loss_out is a 1-element float64 device tensor (or None)."""
+    loss_out is a 1-element float64 device tensor (or None).  noalloc=True
+    calls gcp_loss_grad_noalloc (the library's fixed scratch region instead
+    of the handle's reserved workspace); G and loss_out should then be passed
+    in, or they are allocated here by torch before the call."""
     _require_cuda(A, G, loss_out, scale)
     if A.dtype != t.dtype:
         raise TypeError("model dtype must match the tensor dtype")
@@ -339,11 +345,23 @@ def gcp_loss_grad(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, lo
         smp_p = C.byref(smp)
     spc = sp.c()
     tl = tile.c() if tile is not None else None
-    _check(lib().gcp_loss_grad(t.handle, C.byref(spc), smp_p, _ptr(A), int(R), LOSSES[loss], flags,
-                               _ptr(scale), _ptr(G), _ptr(loss_out), C.byref(tl) if tl is not None else None,
-                               _stream(stream)), "gcp_loss_grad")
+    fn = "gcp_loss_grad_noalloc" if noalloc else "gcp_loss_grad"
+    _check(getattr(lib(), fn)(t.handle, C.byref(spc), smp_p, _ptr(A), int(R), LOSSES[loss], flags,
+                              _ptr(scale), _ptr(G), _ptr(loss_out), C.byref(tl) if tl is not None else None,
+                              _stream(stream)), fn)
     del keep
     return G, loss_out
+
+
+def gcp_loss_grad_noalloc(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, loss: str,
+                          G: torch.Tensor, loss_out: torch.Tensor | None = None, **kw):
+    """gcp_loss_grad_noalloc: gcp_loss_grad on the library's fixed scratch
+    region, for callers that cannot allocate."""
+    return gcp_loss_grad(t, sp, A, R, loss, G=G, loss_out=loss_out, noalloc=True, **kw)
+
+
+def gcp_noalloc_scratch_bytes() -> int:
+    return int(lib().gcp_noalloc_scratch_bytes())
 
 
 def gcp_adam_step(A: torch.Tensor, G: torch.Tensor, B: torch.Tensor, Cm: torch.Tensor, t: int,

@@ -335,4 +335,24 @@ int64_t ceil_div(int64_t a, int64_t b);
 // in to more than 64 KiB when needed.
 gcp_status prepare_lds(const void* fn, size_t bytes, int device);
 
+// Device memory the row-bucketed scatter of gcp_loss_grad may use for its
+// sample entries and per-(row block, workgroup) counts and starts.  Either a
+// reservation of gcp_tensor_reserve (entries / hist / max_samples fixed when
+// it was sized) or, when scratch_bytes > 0, a fixed scratch region of that
+// many bytes carved up afresh by each call.
+struct LGWorkspace {
+    void* base = nullptr;
+    int64_t entries = 0;        // reservation: 16-byte entries
+    int64_t hist = 0;           // reservation: ints in each of counts and starts
+    int64_t max_samples = 0;    // reservation: p + q it was sized for
+    int64_t scratch_bytes = 0;  // > 0: fixed scratch region of this size
+};
+
+// gcp_loss_grad with an explicit bucketed-scatter workspace (the argument
+// checks and launches of loss_grad.hip).
+gcp_status loss_grad_with_workspace(gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
+                                    const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
+                                    void* G_out, double* loss_out, const gcp_tile* tile, const LGWorkspace& ws,
+                                    hipStream_t stream);
+
 }  // namespace gcp

@@ -258,7 +258,8 @@ constexpr int kBucketWgPerCu = 8;              // owner-pass workgroups per CU a
 template <typename T>
 static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
                                    const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
-                                   void* G_out, double* loss_out, const gcp_tile* tile, hipStream_t stream)
+                                   void* G_out, double* loss_out, const gcp_tile* tile, const LGWorkspace& ws,
+                                   hipStream_t stream)
 {
     LGParams<T> P{};
     int64_t n = 0;
@@ -302,7 +303,8 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
             }
         }
         if (req_bucket > 0) bucket_mask = (uint32_t)req_bucket & ((1u << d) - 1) & ~lds_mask;
-        else if (req_bucket < 0 && t->ws && n >= kBucketMinSamples && n <= t->ws_max_samples) bucket_mask = ((1u << d) - 1) & ~lds_mask;
+        else if (req_bucket < 0 && ws.base && n >= kBucketMinSamples && (ws.scratch_bytes > 0 || n <= ws.max_samples))
+            bucket_mask = ((1u << d) - 1) & ~lds_mask;
     }
     // row-block geometry of the bucketed modes
     int br_shift = 0, nb = 0, nbm = 0, spb = 0;
@@ -341,9 +343,23 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
         }
         if (spb % 64 != 0 || spb < 512 || spb > 8192) return set_error(GCP_ERR_ARG, "bucket_block_samples = %d", spb);
         nblocks = ceil_div(n, spb);
-        if (!t->ws) return set_error(GCP_ERR_ARG, "bucketed scatter needs gcp_tensor_reserve first");
-        if (n > t->ws_max_samples || nblocks * spb * (int64_t)nbm > t->ws_entries || (int64_t)nb * nblocks > t->ws_hist)
+        if (!ws.base) return set_error(GCP_ERR_ARG, "bucketed scatter needs gcp_tensor_reserve first");
+        if (ws.scratch_bytes > 0) {
+            // fixed scratch: entries first, then counts and starts
+            const int64_t need = nblocks * spb * (int64_t)nbm * 16 + (int64_t)nb * nblocks * 8;
+            if (need > ws.scratch_bytes) {
+                if (req_bucket >= 0)
+                    return set_error(GCP_ERR_ARG,
+                                     "bucketed scatter of %lld samples needs %lld bytes of scratch, the maximum is %lld",
+                                     (long long)n, (long long)need, (long long)ws.scratch_bytes);
+                // automatic choice: hardware atomics need no scratch
+                bucket_mask = 0;
+                nb = nbm = spb = 0;
+                nblocks = 0;
+            }
+        } else if (n > ws.max_samples || nblocks * spb * (int64_t)nbm > ws.entries || (int64_t)nb * nblocks > ws.hist) {
             return set_error(GCP_ERR_ARG, "workspace reserved by gcp_tensor_reserve is too small for this call");
+        }
     }
 
     // lane shape: one column per lane while any mode scatters with global
@@ -431,9 +447,11 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     P.entry_cap = (int64_t)spb * nbm;
     P.bucket_lds = bucket_lds;
     if (bucket_mask) {
-        P.entries = (uint4*)t->ws;
-        P.hist = (int*)((char*)t->ws + t->ws_entries * 16);
-        P.start = P.hist + t->ws_hist;
+        const int64_t ent = ws.scratch_bytes > 0 ? nblocks * spb * (int64_t)nbm : ws.entries;
+        const int64_t hist = ws.scratch_bytes > 0 ? (int64_t)nb * nblocks : ws.hist;
+        P.entries = (uint4*)ws.base;
+        P.hist = (int*)((char*)ws.base + ent * 16);
+        P.start = P.hist + hist;
     }
 
     if (!accumulate) {
@@ -495,6 +513,16 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     return GCP_OK;
 }
 
+gcp_status loss_grad_with_workspace(gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
+                                    const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
+                                    void* G_out, double* loss_out, const gcp_tile* tile, const LGWorkspace& ws,
+                                    hipStream_t stream)
+{
+    if (t->dt == GCP_F32)
+        return launch_loss_grad<float>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream);
+    return launch_loss_grad<double>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream);
+}
+
 }  // namespace gcp
 
 extern "C" gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, const gcp_samples* smp,
@@ -503,7 +531,10 @@ extern "C" gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, c
 {
     gcp::clear_error();
     if (!t) return gcp::set_error(GCP_ERR_ARG, "tensor is NULL");
-    if (t->dt == GCP_F32)
-        return gcp::launch_loss_grad<float>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, stream);
-    return gcp::launch_loss_grad<double>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, stream);
+    gcp::LGWorkspace ws;
+    ws.base = t->ws;
+    ws.entries = t->ws_entries;
+    ws.hist = t->ws_hist;
+    ws.max_samples = t->ws_max_samples;
+    return gcp::loss_grad_with_workspace(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream);
 }
