@@ -14,7 +14,8 @@
  *   gcp_adam_step  -- Alg. adam-update over the one contiguous parameter
  *                     vector (Sec. 3.1.3).
  * GCP-FedAdam (Alg. gcp-fed-iter) runs many clients' local steps and the
- * server step as one batched launch: gcp_fedadam_create / gcp_fedadam_round.
+ * server step in launches shared by all clients: gcp_fedadam_create /
+ * gcp_fedadam_round.
  *
  * Conventions for every call:
  *   - Indices are 0-based.  Coordinates are int64, row-major [n x d].
@@ -294,9 +295,12 @@ typedef struct gcp_fed_desc {
     int32_t R;                /* rank                                             */
     int32_t tau;              /* local steps per round >= 1                       */
     int32_t loss;             /* gcp_loss                                         */
-    int32_t batched;          /* 1: the clients' local steps run as ONE persistent
-                                 launch per round; 0: one sampled-gradient launch
-                                 and one Adam launch per client and local step    */
+    int32_t batched;          /* 1: every client's local steps run in shared
+                                 launches over all clients (one persistent launch
+                                 per round, or three row-bucketed launches per
+                                 local step, see bucket_modes); 0: one sampled-
+                                 gradient launch and one Adam launch per client
+                                 and local step                                  */
     int32_t use_graph;        /* batched only: capture the round's launches into
                                  a HIP graph on the first round, replay after     */
     int32_t workgroups_per_client; /* batched launch shape, 0 = automatic        */
@@ -309,7 +313,12 @@ typedef struct gcp_fed_desc {
                                  is accumulated in each workgroup's LDS and
                                  flushed once per local step; -1 = automatic
                                  (modes whose largest client block fits), 0 = none */
-    int32_t bucket_modes;     /* batched: bitmask of modes scattered by the row-
+    int32_t bucket_modes;     /* per-client rounds: passed as tile.bucket_modes
+                                 to every gcp_loss_grad call (-1 = that call's
+                                 automatic choice, which row-buckets only when
+                                 the client tensor has a gcp_tensor_reserve
+                                 workspace; 0 = hardware atomics).
+                                 batched: bitmask of modes scattered by the row-
                                  bucketed (sort-by-row) scheme inside the launch:
                                  each client's workgroups sort their samples by
                                  row block, then each owns whole row blocks and
@@ -335,7 +344,36 @@ typedef struct gcp_fed_desc {
     double meta_lr;           /* server Adam rate (meta-rate)                     */
     double beta1, beta2, eps, lower;   /* shared by client and server Adam       */
     const gcp_fed_client* clients;     /* host array of nclients entries         */
+    double barrier_timeout_s; /* persistent launch: a group barrier that waits
+                                 longer than this (device wall clock) gives up
+                                 and fails the round; <= 0 = 10 s              */
 } gcp_fed_desc;
+
+/* How a handle runs its rounds (gcp_fedadam_info). */
+typedef enum gcp_fed_form {
+    GCP_FED_PER_CLIENT = 0,   /* per client and local step: one gcp_loss_grad
+                                 and one gcp_adam_step launch                */
+    GCP_FED_PERSISTENT = 1,   /* one persistent launch for every client and
+                                 local step (group barriers), hardware atomics
+                                 or LDS-private scatter                      */
+    GCP_FED_ROW_BUCKETED = 2  /* per local step three launches over all
+                                 clients: sample and sort by row block, row-
+                                 block owners, Adam                          */
+} gcp_fed_form;
+
+typedef struct gcp_fed_info {
+    int32_t form;                 /* gcp_fed_form                                  */
+    int32_t lds_modes;            /* batched: modes accumulated in LDS per
+                                     workgroup; per-client: the request (-1 =
+                                     decided per launch)                        */
+    int32_t bucket_modes;         /* batched: row-bucketed modes; per-client: the
+                                     request passed to every gcp_loss_grad       */
+    int32_t workgroups_per_client;/* batched                                      */
+    int32_t block, lanes, vec;    /* launch shape of the gradient part           */
+    int32_t bucket_block_samples; /* row-bucketed form: samples per sorted block */
+    int64_t launches_per_round;   /* kernel launches one round issues (per-client
+                                     rounds that may row-bucket: at most)        */
+} gcp_fed_info;
 
 /* Validates the description, copies it, and builds the device-side client
  * table and the row-coverage table of the server step.  Every buffer stays
@@ -346,17 +384,27 @@ typedef struct gcp_fed_desc {
 gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_t stream);
 
 /* Runs round `round` (see above) asynchronously on the stream.  Batched
- * rounds are one persistent kernel for all clients and tau steps plus one
- * server kernel (a HIP graph replay when use_graph is set; the graph is
- * bound to the stream of its first capture).  The persistent kernel's
- * barriers give up after a bounded wait and record GCP_ERR_HIP in the
- * handle's status rather than hang. */
+ * rounds are either one persistent kernel for all clients and tau steps
+ * (GCP_FED_PERSISTENT) or three launches over all clients per local step
+ * (GCP_FED_ROW_BUCKETED), then one server kernel; with use_graph the round's
+ * launches are captured into a HIP graph on the first round and replayed
+ * after (the graph is bound to the stream of its first capture).  The
+ * persistent kernel's group barriers give up after barrier_timeout_s of
+ * device wall clock instead of hanging: the status records GCP_ERR_HIP, the
+ * rest of that round (local steps and the server step) is skipped, and every
+ * later round does nothing until gcp_fedadam_status clears the status.  A
+ * round launched after such a failure has been copied back to the host
+ * returns GCP_ERR_HIP at once, without launching. */
 gcp_status gcp_fedadam_round(gcp_fed f, int64_t round, hipStream_t stream);
 
 /* Synchronises the stream; reports a barrier timeout of a batched round
  * (GCP_ERR_HIP) or a sampling error of any client tensor (GCP_ERR_SAMPLING),
  * and clears them. */
 gcp_status gcp_fedadam_status(gcp_fed f, hipStream_t stream);
+
+/* Fills *out with how the handle runs its rounds (form, scatter modes,
+ * launch shape).  Host only. */
+gcp_status gcp_fedadam_info(gcp_fed f, gcp_fed_info* out);
 
 /* Frees the handle (its graph and device tables; not the caller's buffers). */
 gcp_status gcp_fedadam_destroy(gcp_fed f);

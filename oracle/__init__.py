@@ -337,7 +337,7 @@ def fedadam_round(clients, global_dims, R: int, U: np.ndarray, Bs: np.ndarray, C
                   client_ap: AdamParams, server_ap: AdamParams, max_attempts: int = 64) -> int:
     """One GCP-FedAdam round (Alg. gcp-fed-iter) on float64 state, in place.
 
-    Reading of the algorithm used here (see the design notes):
+    Reading of the algorithm used here:
       1. every client copies the rows of its block from the server model U
          into its local model M_c;
       2. every client runs tau local steps (stratified samples of its block,

@@ -14,9 +14,10 @@
 // and sort by row block (k_fed_sample), row-block owners that accumulate in
 // LDS and store their rows of G_c (k_fed_owner), and Adam (k_fed_adam); the
 // kernel boundaries take the place of the group barriers.  The
-// barrier is a per-client arrival counter in global memory with bounded
-// spinning: all K*W workgroups must be resident (checked at create), and a
-// barrier that waits too long records an error instead of hanging.
+// barrier is a per-client arrival counter in global memory with a wait
+// bounded in device wall-clock time: all K*W workgroups must be resident
+// (checked at create), and a barrier that waits too long records an error
+// and ends the round instead of hanging.
 #include <math.h>
 #include <string.h>
 
@@ -29,7 +30,7 @@
 namespace gcp {
 
 constexpr uint32_t kStatusBarrier = 4u;
-constexpr long kSpinLimit = 1L << 22;
+constexpr double kBarrierTimeoutS = 10.0;      // default wait bound of a group barrier
 constexpr int kFedLdsBudget = 64 * 1024;   // bytes of private client gradient per workgroup
 constexpr int kFedBucketRowBytes = 32 * 1024;   // LDS of one row block in the bucketed scatter
 constexpr int64_t kFedBucketMinSamples = 1 << 14;   // automatic bucketing from this many samples per client step
@@ -56,6 +57,7 @@ struct FedArgs {
     T lr, meta, b1, b2, one_m_b1, one_m_b2, eps, lower;
     double b1d, b2d;
     int* barrier;                  // [K] arrival counters, zero between rounds
+    uint64_t barrier_ticks;        // wait bound of a group barrier, device wall-clock ticks
     const int64_t* round;          // device round number
     uint32_t* status;
     const int64_t* cov_ptr;        // per server row: clients covering it (CSR)
@@ -65,24 +67,38 @@ struct FedArgs {
     int staging_bytes;             // LDS before the private gradient copies
 };
 
-__device__ __forceinline__ void fed_barrier(int* ctr, int target, uint32_t* status)
+__device__ __forceinline__ bool barrier_failed(const uint32_t* status)
+{
+    return (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusBarrier) != 0;
+}
+
+// Group barrier of one client's W workgroups.  Returns false when this or
+// any other barrier of the launch has given up (waited longer than `ticks`
+// of the device wall clock); the caller then ends the round.
+__device__ __forceinline__ bool fed_barrier(int* ctr, int target, uint32_t* status, uint64_t ticks)
 {
     __threadfence();               // this thread's atomics and stores are performed
     __syncthreads();
+    int bad = 0;
     if (threadIdx.x == 0) {
         atomicAdd(ctr, 1);
-        if (!(__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusBarrier)) {
-            for (long spin = 0; __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target; ++spin) {
-                if (spin > kSpinLimit) {
-                    atomicOr(status, kStatusBarrier);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(4);
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (barrier_failed(status)) {
+                bad = 1;
+                break;
             }
+            if (wall_clock64() - t0 > ticks) {
+                atomicOr(status, kStatusBarrier);
+                bad = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
         }
     }
-    __syncthreads();
+    bad = __syncthreads_or(bad);
     __threadfence();               // see the other workgroups' writes
+    return bad == 0;
 }
 
 template <typename T>
@@ -116,11 +132,13 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
     const int64_t nthreads = (int64_t)F.W * blockDim.x;
     const int dd = D > 0 ? D : P.sc.d;
     int arrivals = 0;
+    // a barrier failure of an earlier round stands until the host clears it
+    if (barrier_failed(F.status)) return;
 
     // M_c <- the client's rows of the server model
     for (int k = 0; k < F.d; ++k)
         for (int64_t e = tid; e < C.seg_len[k]; e += nthreads) M[C.seg_dst[k] + e] = F.U[C.seg_src[k] + e];
-    fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+    if (!fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status, F.barrier_ticks)) return;
 
     for (int j = 0; j < F.tau; ++j) {
         const uint64_t step = (uint64_t)(round * F.tau + j);
@@ -146,7 +164,7 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
                 }
             }
         }
-        fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+        if (!fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status, F.barrier_ticks)) return;
         const int64_t t = round * F.tau + j + 1;
         const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
         for (int64_t e = tid; e < nparams; e += nthreads) {
@@ -157,7 +175,7 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
             Cc[e] = cc;
             G[e] = T(0);
         }
-        if (j + 1 < F.tau) fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status);
+        if (j + 1 < F.tau && !fed_barrier(F.barrier + c, (++arrivals) * F.W, F.status, F.barrier_ticks)) return;
     }
 }
 
@@ -267,7 +285,8 @@ __global__ void __launch_bounds__(256) k_fed_adam(const FedArgs<T> F, int j)
 }
 
 // Server step: D = per-row mean over covering clients of U - M_c, then Adam
-// on U with rate meta; also clears the clients' barrier counters.
+// on U with rate meta; also clears the clients' barrier counters.  Skipped
+// (counters still cleared) when a group barrier of the round gave up.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fed_server(const FedArgs<T> F)
 {
@@ -275,7 +294,8 @@ __global__ void __launch_bounds__(256) k_fed_server(const FedArgs<T> F)
     const T c1 = bias_correction<T>(F.b1d, t), c2 = bias_correction<T>(F.b2d, t);
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = gid; e < F.nserver; e += stride) {
+    const int64_t nserver = barrier_failed(F.status) ? 0 : F.nserver;
+    for (int64_t e = gid; e < nserver; e += stride) {
         const int64_t row = e / F.R, col = e - row * F.R;
         const int64_t b = F.cov_ptr[row], end = F.cov_ptr[row + 1];
         T u = F.U[e];
@@ -367,6 +387,10 @@ struct gcp_fed_s {
     int d = 0;
     int W = 1, block = 256, lanes = 0, vec = 0;
     int64_t nserver = 0;
+    uint32_t lds_mask = 0;         // batched: modes accumulated in LDS per workgroup
+    uint32_t bucket_mask = 0;      // batched: row-bucketed modes
+    int spb = 0;                   // row-bucketed: samples per sorted block
+    uint32_t* status_host = nullptr;   // pinned copy of the status word, refreshed after each batched round
     void* dev_clients = nullptr;   // FedClientDev<T>[K]
     void* dev_mptrs = nullptr;
     int* barrier = nullptr;
@@ -449,6 +473,7 @@ static gcp_status fed_build(gcp_fed_s* f)
         }
         lds_max_elems = used / (int64_t)sizeof(T);
     }
+    f->lds_mask = lds_mask;
     f->lds_bytes = (size_t)lds_max_elems * sizeof(T);
     const size_t staging = (size_t)(f->block / 64) * 64 * (8 + 2 * sizeof(T));
 
@@ -483,6 +508,8 @@ static gcp_status fed_build(gcp_fed_s* f)
         }
         GCP_HIP(hipMalloc(&f->bucket_ws, (size_t)std::max<int64_t>(16, ws_off[K])));
         f->bucketed = true;
+        f->bucket_mask = bucket_mask;
+        f->spb = spb;
         f->nb_max = nb_max;
         f->sample_lds = ((staging + f->lds_bytes + 15) & ~(size_t)15) + (size_t)spb * (8 + sizeof(T)) + (size_t)nb_max * 8;
         f->owner_lds = ((((size_t)1 << br_shift) * R * sizeof(T) + 15) & ~(size_t)15) + (size_t)nblocks_c * 8;
@@ -569,6 +596,12 @@ static gcp_status fed_build(gcp_fed_s* f)
     GCP_HIP(hipMemset(f->round, 0, sizeof(int64_t)));
     GCP_HIP(hipMalloc((void**)&f->status, sizeof(uint32_t)));
     GCP_HIP(hipMemset(f->status, 0, sizeof(uint32_t)));
+    GCP_HIP(hipHostMalloc((void**)&f->status_host, sizeof(uint32_t), hipHostMallocDefault));
+    *f->status_host = 0;
+    int clock_khz = 0;
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, f->device) != hipSuccess || clock_khz <= 0)
+        clock_khz = 100000;         // gfx9 wall clock: 100 MHz
+    const double timeout_s = D.barrier_timeout_s > 0 ? D.barrier_timeout_s : kBarrierTimeoutS;
 
     FedArgs<T> a{};
     a.clients = (const FedClientDev<T>*)f->dev_clients;
@@ -592,6 +625,7 @@ static gcp_status fed_build(gcp_fed_s* f)
     a.b1d = D.beta1;
     a.b2d = D.beta2;
     a.barrier = f->barrier;
+    a.barrier_ticks = (uint64_t)(timeout_s * 1000.0 * (double)clock_khz);
     a.round = f->round;
     a.status = f->status;
     a.cov_ptr = f->cov_ptr;
@@ -699,7 +733,7 @@ static gcp_status fed_round_plain(gcp_fed_s* f, int64_t round, hipStream_t strea
     tile.lanes = f->lanes;
     tile.vec = f->vec;
     tile.lds_modes = -1;       // the per-launch automatic choice
-    tile.bucket_modes = 0;
+    tile.bucket_modes = D.bucket_modes;
     for (int j = 0; j < D.tau; ++j) {
         for (int c = 0; c < D.nclients; ++c) {
             const gcp_fed_client& cl = f->clients[c];
@@ -738,6 +772,7 @@ static void fed_free(gcp_fed_s* f)
                     f->cov_lrow, f->bucket_ws};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (f->status_host) (void)hipHostFree(f->status_host);
     (void)hipSetDevice(cur);
     delete f;
 }
@@ -836,12 +871,19 @@ gcp_status gcp_fedadam_round(gcp_fed f, int64_t round, hipStream_t stream)
     clear_error();
     if (!f) return set_error(GCP_ERR_ARG, "handle is NULL");
     if (round < 0) return set_error(GCP_ERR_ARG, "round < 0");
+    // a barrier failure of an earlier batched round, once copied back
+    if (__atomic_load_n(f->status_host, __ATOMIC_RELAXED) & kStatusBarrier)
+        return set_error(GCP_ERR_HIP, "an earlier round's group barrier timed out; gcp_fedadam_status clears it");
     k_fed_set_round<<<1, 1, 0, stream>>>(f->round, round);
     GCP_HIP(hipGetLastError());
     if (!f->desc.batched) return f->dt == GCP_F32 ? fed_round_plain<float>(f, round, stream)
                                                   : fed_round_plain<double>(f, round, stream);
-    if (!f->desc.use_graph)
-        return f->dt == GCP_F32 ? fed_launch_batched<float>(f, stream) : fed_launch_batched<double>(f, stream);
+    if (!f->desc.use_graph) {
+        gcp_status st = f->dt == GCP_F32 ? fed_launch_batched<float>(f, stream) : fed_launch_batched<double>(f, stream);
+        if (st != GCP_OK) return st;
+        GCP_HIP(hipMemcpyAsync(f->status_host, f->status, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+        return GCP_OK;
+    }
     if (!stream) return set_error(GCP_ERR_ARG, "use_graph needs a non-default stream");
     if (f->exec && f->graph_stream != stream) return set_error(GCP_ERR_ARG, "the graph was captured on another stream");
     if (!f->exec) {
@@ -864,6 +906,7 @@ gcp_status gcp_fedadam_round(gcp_fed f, int64_t round, hipStream_t stream)
         f->graph_stream = stream;
     }
     GCP_HIP(hipGraphLaunch(f->exec, stream));
+    GCP_HIP(hipMemcpyAsync(f->status_host, f->status, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     return GCP_OK;
 }
 
@@ -875,6 +918,7 @@ gcp_status gcp_fedadam_status(gcp_fed f, hipStream_t stream)
     uint32_t hs = 0;
     GCP_HIP(hipMemcpy(&hs, f->status, sizeof(hs), hipMemcpyDeviceToHost));
     if (hs) GCP_HIP(hipMemset(f->status, 0, sizeof(uint32_t)));
+    __atomic_store_n(f->status_host, 0u, __ATOMIC_RELAXED);
     gcp_status worst = GCP_OK;
     for (const gcp_fed_client& cl : f->clients) {
         gcp_status st = gcp_device_status(cl.tensor, stream);
@@ -894,7 +938,42 @@ int64_t gcp_struct_size(const char* name)
     if (!strcmp(name, "gcp_tile")) return sizeof(gcp_tile);
     if (!strcmp(name, "gcp_fed_client")) return sizeof(gcp_fed_client);
     if (!strcmp(name, "gcp_fed_desc")) return sizeof(gcp_fed_desc);
+    if (!strcmp(name, "gcp_fed_info")) return sizeof(gcp_fed_info);
     return -1;
+}
+
+gcp_status gcp_fedadam_info(gcp_fed f, gcp_fed_info* out)
+{
+    clear_error();
+    if (!f || !out) return set_error(GCP_ERR_ARG, "NULL argument");
+    gcp_fed_info i{};
+    const gcp_fed_desc& D = f->desc;
+    const int64_t K = D.nclients;
+    if (!D.batched) {
+        i.form = GCP_FED_PER_CLIENT;
+        i.lds_modes = -1;
+        i.bucket_modes = D.bucket_modes;
+        // round number, copy, server; per client and step the gradient (one
+        // launch, two when it row-buckets) and Adam
+        i.launches_per_round = 3 + K * D.tau * (D.bucket_modes != 0 ? 3 : 2);
+    } else if (f->bucketed) {
+        i.form = GCP_FED_ROW_BUCKETED;
+        i.lds_modes = (int32_t)f->lds_mask;
+        i.bucket_modes = (int32_t)f->bucket_mask;
+        i.bucket_block_samples = f->spb;
+        i.launches_per_round = 1 + 1 + 3 * (int64_t)D.tau + 1;
+    } else {
+        i.form = GCP_FED_PERSISTENT;
+        i.lds_modes = (int32_t)f->lds_mask;
+        i.bucket_modes = 0;
+        i.launches_per_round = 1 + 1 + 1;
+    }
+    i.workgroups_per_client = D.batched ? f->W : 0;
+    i.block = f->block;
+    i.lanes = f->lanes;
+    i.vec = f->vec;
+    *out = i;
+    return GCP_OK;
 }
 
 gcp_status gcp_fedadam_destroy(gcp_fed f)

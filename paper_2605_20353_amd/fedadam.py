@@ -2,10 +2,14 @@
 
 The clients' blocks, models, moments and gradient buffers and the server
 model and moments are torch tensors owned here; the rounds run in the HIP
-library: either one persistent launch for all clients and local steps plus one
-server kernel, optionally captured once into a HIP graph and replayed
-(``batched=True``), or one sampled-gradient launch and one Adam launch per
-client and local step (``batched=False``, the per-client baseline).
+library.  Batched rounds (``batched=True``) share their launches among all
+clients: either one persistent launch for every client and local step
+(hardware-atomic or LDS-private scatter), or, with the row-bucketed scatter,
+three launches over all clients per local step (sample and sort, row-block
+owners, Adam); then one server kernel.  The round's launches are captured
+once into a HIP graph and replayed.  Per-client rounds (``batched=False``,
+the baseline) issue one sampled-gradient launch (two when it row-buckets)
+and one Adam launch per client and local step.
 """
 from __future__ import annotations
 
@@ -30,7 +34,17 @@ class gcp_fed_desc(C.Structure):
                 ("p", C.c_int64), ("q", C.c_int64), ("seed", C.c_uint64),
                 ("global_dims", C.c_int64 * 8), ("U", C.c_void_p), ("Bs", C.c_void_p), ("Cs", C.c_void_p),
                 ("lr", C.c_double), ("meta_lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double),
-                ("eps", C.c_double), ("lower", C.c_double), ("clients", C.POINTER(gcp_fed_client))]
+                ("eps", C.c_double), ("lower", C.c_double), ("clients", C.POINTER(gcp_fed_client)),
+                ("barrier_timeout_s", C.c_double)]
+
+
+class gcp_fed_info(C.Structure):
+    _fields_ = [("form", C.c_int32), ("lds_modes", C.c_int32), ("bucket_modes", C.c_int32),
+                ("workgroups_per_client", C.c_int32), ("block", C.c_int32), ("lanes", C.c_int32),
+                ("vec", C.c_int32), ("bucket_block_samples", C.c_int32), ("launches_per_round", C.c_int64)]
+
+
+FORMS = {0: "per_client", 1: "persistent", 2: "row_bucketed"}
 
 
 def _declare():
@@ -45,6 +59,8 @@ def _declare():
     L.gcp_fedadam_status.restype = C.c_int
     L.gcp_fedadam_destroy.argtypes = [C.c_void_p]
     L.gcp_fedadam_destroy.restype = C.c_int
+    L.gcp_fedadam_info.argtypes = [C.c_void_p, C.POINTER(gcp_fed_info)]
+    L.gcp_fedadam_info.restype = C.c_int
     L._fed_declared = True
     return L
 
@@ -64,11 +80,14 @@ class FedConfig:
     eps: float = 1e-8
     lower: float = 0.0
     max_attempts: int = 64
+    barrier_timeout_s: float = 0.0      # persistent launch's group-barrier wait bound; 0 = library default
 
 
 @dataclass
 class FedTile:
-    """Launch shape of the batched round (0 = library default)."""
+    """Launch shape of the batched round (0 = library default).  For
+    per-client rounds only bucket_modes is used: it is passed to every
+    gcp_loss_grad call (-1 = that call's automatic choice)."""
     workgroups_per_client: int = 0
     block: int = 0
     lanes: int = 0
@@ -97,7 +116,10 @@ class FedAdam:
     """GCP-FedAdam state and rounds.
 
     clients: list of (SparseTensor in block-local coordinates, row_base per mode).
-    U0: initial server model [sum_k I_k, R] (copied)."""
+    U0: initial server model [sum_k I_k, R] (copied).
+    Per-client rounds with tile.bucket_modes != 0 reserve each client
+    tensor's row-bucketing workspace (gcp_tensor_reserve) so that every
+    gcp_loss_grad call may choose that scatter."""
 
     def __init__(self, clients, global_dims, U0: torch.Tensor, cfg: FedConfig, batched: bool = True,
                  use_graph: bool = True, tile: FedTile | None = None, stream: torch.cuda.Stream | None = None):
@@ -107,6 +129,8 @@ class FedAdam:
         self.batched = bool(batched)
         self.use_graph = bool(use_graph) and self.batched
         self.tile = tile or FedTile()
+        if not self.batched and tile is None:
+            self.tile = FedTile(bucket_modes=0)      # the per-client baseline's default: hardware atomics
         dev = U0.device
         self.dtype = U0.dtype
         self.U = U0.detach().reshape(-1).contiguous().clone()
@@ -117,6 +141,8 @@ class FedAdam:
             n = t.model_rows * cfg.R
             z = lambda: torch.zeros(n, dtype=self.dtype, device=dev)
             self.clients.append(FedClient(t, [int(b) for b in base], z(), z(), z(), z()))
+            if not self.batched and self.tile.bucket_modes != 0 and t.reserved_samples < cfg.p + cfg.q:
+                t.reserve(cfg.p + cfg.q, cfg.R)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
         self._h = None
         self._create()
@@ -154,6 +180,7 @@ class FedAdam:
         d.lr, d.meta_lr = cfg.lr, cfg.meta_lr
         d.beta1, d.beta2, d.eps, d.lower = cfg.beta1, cfg.beta2, cfg.eps, cfg.lower
         d.clients = C.cast(arr, C.POINTER(gcp_fed_client))
+        d.barrier_timeout_s = cfg.barrier_timeout_s
         return d
 
     def _create(self):
@@ -185,16 +212,29 @@ class FedAdam:
             pass
 
     # ------------------------------------------------------------- rounds --
-    def round(self, r: int) -> None:
+    def round(self, r: int, check: bool = False) -> None:
         """Run round r on the handle's stream; the caller's current stream
-        waits for it."""
+        waits for it.  A barrier failure of an earlier batched round raises
+        here once its status has reached the host; check=True also waits for
+        this round and raises on any device error it recorded."""
         cur = torch.cuda.current_stream()
         self.stream.wait_stream(cur)
         G._check(_declare().gcp_fedadam_round(self._h, int(r), G._stream(self.stream)), "gcp_fedadam_round")
         cur.wait_stream(self.stream)
+        if check:
+            self.status()
 
     def status(self) -> None:
         G._check(_declare().gcp_fedadam_status(self._h, G._stream(self.stream)), "gcp_fedadam_status")
+
+    def info(self) -> dict:
+        """How the handle runs its rounds (gcp_fedadam_info)."""
+        i = gcp_fed_info()
+        G._check(_declare().gcp_fedadam_info(self._h, C.byref(i)), "gcp_fedadam_info")
+        return {"form": FORMS.get(i.form, i.form), "lds_modes": i.lds_modes, "bucket_modes": i.bucket_modes,
+                "workgroups_per_client": i.workgroups_per_client, "block": i.block, "lanes": i.lanes,
+                "vec": i.vec, "bucket_block_samples": i.bucket_block_samples,
+                "launches_per_round": i.launches_per_round}
 
     # -------------------------------------------------------------- state --
     def snapshot(self):
@@ -226,8 +266,12 @@ class Batched(FedAdam):
 
 class Plain(FedAdam):
     """GCP-FedAdam with one sampled-gradient launch and one Adam launch per
-    client and local step (the per-client reference)."""
+    client and local step (the per-client reference).  scatter="atomic"
+    forces hardware atomics; "auto" reserves each client's workspace and
+    lets every gcp_loss_grad call choose (row-bucketed at large sample
+    counts)."""
 
     def __init__(self, clients, global_dims, U0: torch.Tensor, cfg: FedConfig,
-                 stream: torch.cuda.Stream | None = None):
-        super().__init__(clients, global_dims, U0, cfg, batched=False, use_graph=False, stream=stream)
+                 stream: torch.cuda.Stream | None = None, scatter: str = "atomic"):
+        tile = FedTile(bucket_modes=0 if scatter == "atomic" else -1)
+        super().__init__(clients, global_dims, U0, cfg, batched=False, use_graph=False, tile=tile, stream=stream)

@@ -8,7 +8,8 @@ samples and factors element by element:
 where bound is the oracle's first-order rounding-error bound for the GPU's
 arithmetic (unit roundoff 2^-24 in float32, 2^-53 in float64), valid for any
 order of the additions (atomics, per-workgroup partial sums, row-block
-owners), plus the same bound at 2^-53 for the oracle's own FP64 rounding.
+owners), plus the same bound at 2^-53 for the oracle's own FP64 rounding
+(the bound is first-order in the unit roundoff, so that is the first scaled).
 SAFETY = 2 covers the second-order terms the first-order bound drops; floor
 (1e-37) only matters for elements whose bound is zero or underflows.
 The per-mode Frobenius relative error (<= 1e-5 in float32, <= 1e-12 in
@@ -40,10 +41,12 @@ def frob_rel_errs(g_gpu, g_ora, dims, R):
 
 
 def element_bound(dims, R, A64, coords, x, w, loss, dtype, n_semi=0):
-    """Allowed |G^ - G| per element for a gradient computed in `dtype`."""
-    b = oracle.grad_error_bound(dims, R, A64, coords, x, w, loss, _u(dtype), n_semi=n_semi)
-    b64 = oracle.grad_error_bound(dims, R, A64, coords, x, w, loss, oracle.U_F64, n_semi=n_semi)
-    return SAFETY * (b + b64) + 1e-37
+    """Allowed |G^ - G| per element for a gradient computed in `dtype`.  The
+    bound is first-order in the unit roundoff, so the oracle's own FP64
+    rounding adds the same bound scaled by 2^-53 / u."""
+    u = _u(dtype)
+    b = oracle.grad_error_bound(dims, R, A64, coords, x, w, loss, u, n_semi=n_semi)
+    return SAFETY * b * (1.0 + oracle.U_F64 / u) + 1e-37
 
 
 def assert_grad_close(g_gpu, g_ora, dims, R, A64, coords, x, w, loss, dtype, n_semi=0, what="", scale=1.0):

@@ -143,6 +143,22 @@ def test_fp64_automatic_bucketing_at_large_sample_counts(gpu):
         assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
 
 
+FP32_TOL = 1e-5
+
+
+def _assert_state_matches(fed, Uo, ocl, tol, what):
+    """U and every client's M_c, B_c, C_c against the oracle's round state.
+    B_c (the first moment, (1 - beta1) times a sum of sampled gradients) is
+    not invariant to the gradients' scale, so it catches magnitude errors
+    that Adam's sign-like early steps hide in U and M_c."""
+    assert _rel(fed.U.double().cpu().numpy(), Uo) <= tol, f"{what}: U"
+    for c, (cl, oc) in enumerate(zip(fed.clients, ocl)):
+        assert _rel(cl.M.double().cpu().numpy(), oc.M) <= tol, f"{what}: M_{c}"
+        assert _rel(cl.B.double().cpu().numpy(), oc.B) <= tol, f"{what}: B_{c}"
+        assert _rel(cl.C.double().cpu().numpy(), oc.C) <= tol, f"{what}: C_{c}"
+        assert torch.count_nonzero(cl.G).item() == 0, f"{what}: G_{c} not left zeroed"
+
+
 @pytest.mark.parametrize("shape", [(32, 1), (16, 2), (8, 4)])
 def test_fp32_batched_equals_plain_and_oracle(gpu, shape):
     gdims, grid, R = [200, 160, 60], (4, 2, 2), 32
@@ -150,20 +166,107 @@ def test_fp32_batched_equals_plain_and_oracle(gpu, shape):
     U0 = 0.1 + 0.9 * synth.init_model(gdims, R, 2711, dtype=torch.float64)
     cfg = FedConfig(R=R, tau=4, loss="poisson", p=1024, q=1024, seed=11, lr=1e-3, meta_lr=1e-3, lower=0.0)
     feds = {}
-    for mode in ("batched_graph", "plain", "batched_graph_bucketed"):
-        tile = FedTile(lanes=shape[0], vec=shape[1], bucket_modes=7 if mode.endswith("bucketed") else 0)
+    # the client blocks' modes all fit the LDS budget, so the bucketed mode
+    # turns LDS-private accumulation off to really row-bucket every mode
+    tiles = {"batched_graph": FedTile(lanes=shape[0], vec=shape[1], bucket_modes=0),
+             "plain": FedTile(lanes=shape[0], vec=shape[1], bucket_modes=0),
+             "batched_graph_bucketed": FedTile(lanes=shape[0], vec=shape[1], lds_modes=0, bucket_modes=7)}
+    forms = {"batched_graph": "persistent", "plain": "per_client", "batched_graph_bucketed": "row_bucketed"}
+    for mode, tile in tiles.items():
         fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg,
                       batched=mode != "plain", use_graph=mode.startswith("batched_graph"), tile=tile)
+        info = fed.info()
+        assert info["form"] == forms[mode], (mode, info)
+        if mode.endswith("bucketed"):
+            assert info["bucket_modes"] == 7 and info["lds_modes"] == 0, info
         for r in range(2):
             fed.round(r)
         fed.status()
         feds[mode] = fed
-    Up = feds["plain"].U.double().cpu().numpy()
-    Uo, _ = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    for mode, fed in feds.items():
+        _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"{mode} {shape}")
     for mode in ("batched_graph", "batched_graph_bucketed"):
-        Ub = feds[mode].U.double().cpu().numpy()
-        assert _rel(Ub, Up) <= 1e-5, mode
-        assert _rel(Ub, Uo) <= 1e-5, mode
+        for cb, cp in zip(feds[mode].clients, feds["plain"].clients):
+            assert _rel(cb.B.double().cpu().numpy(), cp.B.double().cpu().numpy()) <= FP32_TOL, mode
+
+
+# client blocks 1200 x 1000 x 200 at rank 32 in float32: modes 0 and 1 exceed
+# the 64 KiB LDS budget of a batched client (150 and 125 KiB), mode 2 fits
+BIG = dict(gdims=[2400, 2000, 400], grid=(2, 2, 2), R=32, nmin=3000, nmax=20000)
+
+
+@pytest.mark.parametrize("lds", ["auto", "none"])
+def test_fp32_row_bucketed_round_matches_oracle(gpu, lds):
+    """The FP32 row-bucketed batched round -- k_fed_sample / k_fed_owner with
+    eight lanes of four columns, the form config-5 rounds take -- against the
+    oracle's FedAdam rounds: 2^13 + 2^13 samples per client step (the
+    automatic choice row-buckets from 2^14), three local steps, two rounds.
+    With the automatic LDS choice mode 2 stays LDS-private next to the two
+    bucketed modes; without it every mode is bucketed."""
+    gdims, grid, R = BIG["gdims"], BIG["grid"], BIG["R"]
+    blocks = _blocks(gdims, grid, R, BIG["nmin"], BIG["nmax"], seed=2631)
+    U0 = 0.1 + 0.9 * synth.init_model(gdims, R, 2731, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=3, loss="poisson", p=1 << 13, q=1 << 13, seed=13, lr=1e-3, meta_lr=1e-3, lower=0.0)
+    tile = FedTile() if lds == "auto" else FedTile(lds_modes=0)
+    say(f"fedadam fp32 row-bucketed, lds {lds}")
+    fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg, tile=tile)
+    info = fed.info()
+    assert info["form"] == "row_bucketed", info
+    assert (info["lanes"], info["vec"]) == (8, 4), info
+    assert info["bucket_modes"] == (3 if lds == "auto" else 7) and info["lds_modes"] == (4 if lds == "auto" else 0), info
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"row-bucketed lds={lds}")
+
+
+def test_fp32_per_client_automatic_scatter_matches_oracle(gpu):
+    """Per-client rounds with each gcp_loss_grad call's automatic scatter
+    (row-bucketed at 2^16 samples, on the client workspaces the Plain class
+    reserves) against the oracle."""
+    from paper_2605_20353_amd.fedadam import Plain
+    gdims, grid, R = BIG["gdims"], BIG["grid"], BIG["R"]
+    blocks = _blocks(gdims, grid, R, BIG["nmin"], BIG["nmax"], seed=2632)
+    U0 = 0.1 + 0.9 * synth.init_model(gdims, R, 2732, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=1 << 15, q=1 << 15, seed=17, lr=1e-3, meta_lr=1e-3, lower=0.0)
+    fed = Plain(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg, scatter="auto")
+    info = fed.info()
+    assert info["form"] == "per_client" and info["bucket_modes"] == -1, info
+    assert all(cl.tensor.reserved_samples >= cfg.p + cfg.q for cl in fed.clients)
+    fed.round(0)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 1, torch.float32)
+    _assert_state_matches(fed, Uo, ocl, FP32_TOL, "per-client automatic scatter")
+
+
+def test_barrier_timeout_fails_the_round_cleanly(gpu):
+    """A persistent round whose group barriers may wait no time at all: the
+    first early arrival gives up (workgroups without samples reach the
+    barrier after the gradient long before those with samples), every
+    workgroup leaves the launch, the server step is skipped, U is unchanged,
+    the next round is refused on the host, and the status reports and clears
+    the failure."""
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2633)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2733, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=3, loss="poisson", p=64, q=64, seed=3, lr=1e-2, meta_lr=1e-2, lower=0.0,
+                    barrier_timeout_s=1e-9)
+    fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, use_graph=False,
+                  tile=FedTile(workgroups_per_client=4, block=64, bucket_modes=0))
+    assert fed.info()["form"] == "persistent"
+    U_before = fed.U.clone()
+    fed.round(0)
+    torch.cuda.synchronize()
+    assert torch.equal(fed.U, U_before)
+    with pytest.raises(G.GCPError) as e:
+        fed.round(1)
+    assert e.value.code == G.GCP_ERR_HIP
+    with pytest.raises(G.GCPError) as e:
+        fed.status()
+    assert e.value.code == G.GCP_ERR_HIP
+    fed.status()                                    # cleared
 
 
 @pytest.mark.parametrize("scatter", ["atomic", "bucketed"])

@@ -1,9 +1,11 @@
 """GPU parity: the HIP path against the FP64 CPU oracle, through the C ABI.
 
-Samples must match bit for bit.  Gradients are compared per mode as
-||G_gpu - G_oracle||_F / ||G_oracle||_F with the oracle fed the same factors
-(float32 factors upcast to float64): <= 1e-12 for the float64 build and
-<= 1e-5 for float32.  Sampled objectives: same relative bounds.
+Samples must match bit for bit.  Gradients are compared with the oracle fed
+the same factors (float32 factors upcast to float64) element by element --
+every element within the rounding-error bound of the GPU's arithmetic for any
+summation order (parity_util) -- and per mode as ||G_gpu - G_oracle||_F /
+||G_oracle||_F: <= 1e-12 for the float64 build and <= 1e-5 for float32.
+Sampled objectives: same relative bounds.
 """
 import math
 import sys
@@ -15,6 +17,7 @@ import torch
 import oracle
 from paper_2605_20353_amd import _lib as G
 from paper_2605_20353_amd import synth
+from parity_util import assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -58,24 +61,33 @@ def model(dims, R, dtype, gpu, seed=7, dist="uniform", lo=0.2):
     return A.to(dtype).to(gpu).contiguous()
 
 
-def split_rel_err(g_gpu, g_ora, dims, R):
-    g_gpu = g_gpu.reshape(-1, R)
-    g_ora = g_ora.reshape(-1, R)
-    errs, off = [], 0
-    for n in dims:
-        a, b = g_gpu[off:off + n], g_ora[off:off + n]
-        nb = np.linalg.norm(b)
-        errs.append(np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a))
-        off += n
-    return max(errs)
+class Ref:
+    """The oracle's gradient and objective of one sample set, and the
+    per-element check of a GPU gradient against them."""
+
+    def __init__(self, dims, R, A, coords, x, w, loss, n_semi=0):
+        self.dims, self.R, self.loss, self.n_semi = list(dims), R, loss, n_semi
+        self.A64 = A.double().cpu().numpy().reshape(-1)
+        self.coords, self.x, self.w = coords, x, w
+        self.G, self.F = oracle.loss_grad(self.dims, R, self.A64, coords, x, w, loss, n_semi=n_semi)
+
+    def check(self, Gg, dtype, what="", scale=1.0, bound_scale=None):
+        """Gg ~ scale * G element by element; bound_scale widens the bound
+        (several results added together)."""
+        bs = abs(scale) if bound_scale is None else bound_scale
+        return assert_grad_close(Gg.double().cpu().numpy(), scale * np.asarray(self.G), self.dims, self.R, self.A64,
+                                 self.coords, self.x, self.w, self.loss, dtype, n_semi=self.n_semi, what=str(what),
+                                 scale=bs)
+
+    def check_loss(self, Lg, dtype, factor=1.0):
+        assert abs(Lg.item() - factor * self.F) <= TOL[dtype] * abs(factor * self.F), (Lg.item(), self.F)
 
 
-def oracle_grad(t_ora, dims, R, A, loss, sp: G.SampleParams):
+def oracle_ref(t_ora, dims, R, A, loss, sp: G.SampleParams) -> Ref:
     semi = sp.kind == "semi_stratified"
     sc, sx, sw = oracle.sample_stratified(t_ora, sp.p, sp.q, sp.seed, sp.step, sp.client,
                                           sp.max_attempts, semi=semi)
-    A64 = A.double().cpu().numpy().reshape(-1)
-    return oracle.loss_grad(dims, R, A64, sc, sx, sw, loss, n_semi=sp.p if semi else 0)
+    return Ref(dims, R, A, sc, sx, sw, loss, n_semi=sp.p if semi else 0)
 
 
 # --------------------------------------------------------------- sampling --
@@ -121,11 +133,11 @@ def test_samples_bit_exact_mostly_full_tensor(gpu, dtype):
     assert not np.isin(np.ravel_multi_index(oc[p:].T, dims), cells).any()
     R = 8
     A = model(dims, R, dtype, gpu)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
     Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson")
     t_gpu.status()
-    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
-    assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+    ref.check(Gg, dtype, "mostly full")
+    ref.check_loss(Lg, dtype)
 
 
 def test_samples_depend_on_step_seed_client(gpu):
@@ -215,7 +227,7 @@ def test_mixed_radix_keys_match_oracle(gpu, dtype, name):
             assert all(list(zc[s]) != planted[s // 2] for s in range(0, q, 2))
         else:                         # semi-stratified keeps the first candidate
             assert all(list(zc[s]) == planted[s // 2] for s in range(0, q, 2))
-        Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+        ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
         tiles = [G.Tile(), G.Tile(lds_modes=0, bucket_modes=0)]
         if name == "4way_64bit":
             t_gpu.reserve(sp.n, R)
@@ -223,10 +235,10 @@ def test_mixed_radix_keys_match_oracle(gpu, dtype, name):
         for tile in tiles:
             Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=tile)
             t_gpu.status()
-            assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype], (kind, tile)
-            assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+            ref.check(Gg, dtype, (kind, tile))
+            ref.check_loss(Lg, dtype)
         Gm, _ = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", samples=(c, x, w))
-        assert split_rel_err(Gm.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+        ref.check(Gm, dtype, (kind, "materialised"))
 
 
 # --------------------------------------------------------------- gradient --
@@ -242,9 +254,9 @@ def test_fused_loss_grad_matches_oracle(gpu, dtype, loss, name):
     say(f"loss_grad {name} {loss} {dtype}")
     Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, loss)
     t_gpu.status()
-    Go, Fo = oracle_grad(t_ora, dims, R, A, loss, sp)
-    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
-    assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+    ref = oracle_ref(t_ora, dims, R, A, loss, sp)
+    ref.check(Gg, dtype, (name, loss))
+    ref.check_loss(Lg, dtype)
 
 
 def _shapes(R, dtype):
@@ -263,18 +275,17 @@ def test_every_tile_matches_oracle(gpu, dtype, name):
     t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
     A = model(dims, R, dtype, gpu)
     sp = G.SampleParams("stratified", 777, 555, seed=3, step=1)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
     for lanes, vec in _shapes(R, dtype):
         for block in (64, 256, 1024):
             for lds in (0, (1 << len(dims)) - 1):
                 tile = G.Tile(lanes=lanes, vec=vec, block=block, lds_modes=lds)
                 Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=tile)
-                err = split_rel_err(Gg.double().cpu().numpy(), Go, dims, R)
-                assert err <= TOL[dtype], (lanes, vec, block, lds, err)
-                assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+                ref.check(Gg, dtype, (lanes, vec, block, lds))
+                ref.check_loss(Lg, dtype)
     # a small grid forces many chunks per wave (grid-stride path)
     Gg, _ = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(grid=1, block=64))
-    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
+    ref.check(Gg, dtype, "grid 1")
 
 
 BUCKET_TILES = [
@@ -299,7 +310,7 @@ def test_bucketed_scatter_every_lane_shape(gpu, dtype, name):
     t_gpu.reserve(sum(pq), R)
     A = model(dims, R, dtype, gpu)
     sp = G.SampleParams("stratified", pq[0], pq[1], seed=37, step=4)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
     every = (1 << len(dims)) - 1
     for lanes, vec in _shapes(R, dtype):
         for lds in (0, 1):
@@ -308,34 +319,34 @@ def test_bucketed_scatter_every_lane_shape(gpu, dtype, name):
             say(f"bucketed shape {name} {dtype} {tl}")
             Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(**tl))
             t_gpu.status()
-            err = split_rel_err(Gg.double().cpu().numpy(), Go, dims, R)
-            assert err <= TOL[dtype], (tl, err)
-            assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+            ref.check(Gg, dtype, tl)
+            ref.check_loss(Lg, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("loss", ["poisson", "gaussian"])
+@pytest.mark.parametrize("loss", LOSSES)
 @pytest.mark.parametrize("pq", [(70000, 50001), (3000, 2000)])
 def test_bucketed_scatter_matches_oracle(gpu, dtype, loss, pq):
     """Row-bucketed (sort-by-row) scatter, alone and mixed with the LDS and
-    atomic strategies, ragged sample counts, against the oracle."""
-    t_gpu, t_ora, dims, R = make_case("r32", dtype, gpu)
+    atomic strategies, ragged sample counts, every loss, against the oracle."""
+    t_gpu, t_ora, dims, R = make_case("r32", dtype, gpu, binary=(loss == "bernoulli_logit"))
     t_gpu.reserve(sum(pq), R)
-    A = model(dims, R, dtype, gpu, dist="normal" if loss == "gaussian" else "uniform")
+    A = model(dims, R, dtype, gpu, dist="uniform" if loss == "poisson" else "normal")
     sp = G.SampleParams("stratified", pq[0], pq[1], seed=31, step=2)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, loss, sp)
+    ref = oracle_ref(t_ora, dims, R, A, loss, sp)
     for tl in BUCKET_TILES:
         say(f"bucketed {dtype} {loss} {pq} {tl}")
         Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, loss, tile=G.Tile(**tl))
         t_gpu.status()
-        assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype], tl
-        assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
-    # a scale and accumulation go through the bucketed path too
+        ref.check(Gg, dtype, tl)
+        ref.check_loss(Lg, dtype)
+    # a scale and accumulation go through the bucketed path too: two halves
+    # added, each within half the bound, plus the rounding of their sum
     scale = torch.tensor([0.5], dtype=dtype, device=gpu)
     Gs, _ = G.gcp_loss_grad(t_gpu, sp, A, R, loss, scale=scale, tile=G.Tile(bucket_modes=7, lds_modes=0))
     Gs, _ = G.gcp_loss_grad(t_gpu, sp, A, R, loss, G=Gs, accumulate=True, scale=scale,
                             tile=G.Tile(bucket_modes=7, lds_modes=0))
-    assert split_rel_err(Gs.double().cpu().numpy(), Go, dims, R) <= 4 * TOL[dtype]
+    ref.check(Gs, dtype, "scaled and accumulated", bound_scale=2.0)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -344,10 +355,10 @@ def test_bucketed_scatter_4way_r64(gpu, dtype):
     t_gpu.reserve(40000, R)
     A = model(dims, R, dtype, gpu)
     sp = G.SampleParams("stratified", 20000, 19999, seed=5, step=9)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
     for tl in (dict(bucket_modes=15, lds_modes=0), dict(bucket_modes=15, lds_modes=0, bucket_lds_bytes=8192)):
         Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(**tl))
-        assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype], tl
+        ref.check(Gg, dtype, tl)
 
 
 def test_bucketed_scatter_needs_workspace(gpu):
@@ -369,10 +380,10 @@ def test_materialised_equals_fused(gpu, dtype):
     smp = G.gcp_sample(t_gpu, sp)
     Gm, Lm = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", samples=smp)
     Gf, Lf = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson")
-    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
-    for Gx, Lx in ((Gm, Lm), (Gf, Lf)):
-        assert split_rel_err(Gx.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
-        assert abs(Lx.item() - Fo) <= TOL[dtype] * abs(Fo)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
+    for name, (Gx, Lx) in (("materialised", (Gm, Lm)), ("fused", (Gf, Lf))):
+        ref.check(Gx, dtype, name)
+        ref.check_loss(Lx, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -382,9 +393,9 @@ def test_semi_stratified_grad_matches_oracle(gpu, dtype, loss):
     A = model(dims, R, dtype, gpu, dist="normal" if loss != "poisson" else "uniform")
     sp = G.SampleParams("semi_stratified", 1000, 1200, seed=8, step=3)
     Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, loss)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, loss, sp)
-    assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
-    assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+    ref = oracle_ref(t_ora, dims, R, A, loss, sp)
+    ref.check(Gg, dtype, ("semi-stratified", loss))
+    ref.check_loss(Lg, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -394,12 +405,12 @@ def test_uniform_dense_grad_matches_oracle(gpu, dtype):
     t = G.DenseTensor(dims, X.to(dtype).to(gpu))
     A = model(dims, R, dtype, gpu, dist="normal")
     sp = G.SampleParams("uniform", 5000, 0, seed=4, step=0)
+    oc, ox, ow = oracle.sample_uniform(dims, X.to(dtype).double().numpy(), 5000, 4, 0)
+    ref = Ref(dims, R, A, oc, ox, ow, "gaussian")
     for lds in (-1, 0, 15):
         Gg, Lg = G.gcp_loss_grad(t, sp, A, R, "gaussian", tile=G.Tile(lds_modes=lds))
-        oc, ox, ow = oracle.sample_uniform(dims, X.to(dtype).double().numpy(), 5000, 4, 0)
-        Go, Fo = oracle.loss_grad(dims, R, A.double().cpu().numpy(), oc, ox, ow, "gaussian")
-        assert split_rel_err(Gg.double().cpu().numpy(), Go, dims, R) <= TOL[dtype]
-        assert abs(Lg.item() - Fo) <= TOL[dtype] * abs(Fo)
+        ref.check(Gg, dtype, ("uniform", lds))
+        ref.check_loss(Lg, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -407,16 +418,17 @@ def test_flags_scale_accumulate_loss_only(gpu, dtype):
     t_gpu, t_ora, dims, R = make_case("cfg1_50x40x30", dtype, gpu)
     A = model(dims, R, dtype, gpu)
     sp = G.SampleParams("stratified", 500, 500, seed=1, step=0)
-    Go, Fo = oracle_grad(t_ora, dims, R, A, "poisson", sp)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
     scale = torch.tensor([-2.5], dtype=dtype, device=gpu)
     Gs, Ls = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", scale=scale)
-    assert split_rel_err(Gs.double().cpu().numpy(), -2.5 * Go, dims, R) <= TOL[dtype]
-    assert abs(Ls.item() - Fo) <= TOL[dtype] * abs(Fo)            # objective not scaled
+    ref.check(Gs, dtype, "scaled", scale=-2.5)
+    ref.check_loss(Ls, dtype)                                      # objective not scaled
     Ga, La = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", G=Gs.clone(), loss_out=Ls.clone(), accumulate=True)
-    assert split_rel_err(Ga.double().cpu().numpy(), -1.5 * Go, dims, R) <= 10 * TOL[dtype]
-    assert abs(La.item() - 2 * Fo) <= TOL[dtype] * abs(2 * Fo)
+    # -2.5 G (bound 2.5 b) plus G (bound b), plus the rounding of their sum
+    ref.check(Ga, dtype, "accumulated", scale=-1.5, bound_scale=4.5)
+    ref.check_loss(La, dtype, factor=2.0)
     _, Lo = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", loss_only=True)
-    assert abs(Lo.item() - Fo) <= TOL[dtype] * abs(Fo)
+    ref.check_loss(Lo, dtype)
 
 
 # ------------------------------------------------------------------- Adam --
