@@ -37,7 +37,7 @@ import torch  # noqa: E402
 from paper_2605_20353_amd import _lib as G  # noqa: E402
 from paper_2605_20353_amd import autotune, synth  # noqa: E402
 from paper_2605_20353_amd.autograd import gcp_loss  # noqa: E402
-from paper_2605_20353_amd.fedadam import FedAdam, FedConfig  # noqa: E402
+from paper_2605_20353_amd.fedadam import FedAdam, FedConfig, FedTile, Plain  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 DIMS = [10000, 8000, 6000]
@@ -69,9 +69,10 @@ def algorithmic_bytes(d: int, R: int, p: int, q: int, w: int = 4) -> int:
     return p * per_nz + q * per_z
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+def traffic_record():
+    """The committed rocprofv3 counter summary of the sampled-gradient call
+    (DRAM bytes per launch and the tile it was taken at), if it was taken on
+    the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -79,7 +80,25 @@ def measured_traffic():
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+CEILINGS_FILE = os.path.join(ROOT, "profiles", "ceilings.json")
+
+
+def binding_ceiling(kernel_ms: float):
+    """The sampled-gradient call's lower bound from the measured hardware
+    ceilings (profiles/ceilings.json, written by --ceilings), if present."""
+    try:
+        with open(CEILINGS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    lb = c.get("config2_call_lower_bound_ms")
+    if not lb:
+        return None
+    return {"name": c.get("binding"), "lower_bound_ms": lb, "frac": round(lb / kernel_ms, 4),
+            "source": "profiles/ceilings.json (bench.py --ceilings)"}
 
 
 TILE_FIELDS = ("lanes", "vec", "block", "grid", "lds_modes", "bucket_modes", "bucket_lds_bytes",
@@ -178,9 +197,20 @@ def _median_ms(fn, reps: int, warmup: int) -> float:
 def run_fedadam(dev, rounds: int, tune: bool = True):
     """GCP-FedAdam, 64 clients on a 4x4x4 block grid over 20000x20000x2000,
     1e5..5e6 nonzeros per client (log-uniform), rank 32 FP32, tau = 10 local
-    steps of 2^16 + 2^16 samples, then the server step: ms per round for
-    per-client launches and for the batched persistent launch (graph replay,
-    autotuned launch shape)."""
+    steps of 2^16 + 2^16 samples, then the server step.  Median ms per round
+    of four forms on the same state:
+      plain_atomic  per-client launches (a gcp_loss_grad and a gcp_adam_step
+                    per client and local step), hardware-atomic scatter;
+      plain_auto    per-client launches, each call's automatic scatter
+                    (row-bucketed at 2^17 samples, on reserved workspaces);
+      persistent    one persistent launch for every client and local step
+                    (group barriers, atomic and LDS-private scatter), graph
+                    replay, the autotuner's best persistent shape;
+      bucketed      three launches over all clients per local step (sample
+                    and sort, row-block owners, Adam), graph replay, the
+                    autotuner's best row-bucketed shape.
+    The speedup is the best batched form against the best per-client form,
+    so the choice of scatter is not counted as a gain of batching."""
     gd, grid, R = [20000, 20000, 2000], (4, 4, 4), 32
     log("fedadam: generating 64 client blocks")
     blocks = synth.fed_blocks(gd, grid, R, 1e5, 5e6, seed=2610, device=dev)
@@ -193,24 +223,42 @@ def run_fedadam(dev, rounds: int, tune: bool = True):
                     lower=0.0)
     out = {"workload": "GCP-FedAdam, 64 clients (4x4x4 grid over 20000x20000x2000), "
                        f"{nnz} nonzeros, rank 32 FP32, tau 10 x (2^16 + 2^16) samples per client",
-           "nnz": nnz}
-    plain = FedAdam(clients, gd, U0, cfg, batched=False)
-    out["plain_ms_per_round"] = _median_ms(lambda: plain.round(0), rounds, 1)
-    plain.status()
-    plain.close()
-    fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True)
-    tile = autotune.tune_fedadam(fed, rounds=1, warmup=1, use_cache=False) if tune else fed.tile
-    out["batched_tile"] = {"workgroups_per_client": tile.workgroups_per_client, "block": tile.block,
-                           "lanes": tile.lanes, "vec": tile.vec, "lds_modes": tile.lds_modes,
-                           "bucket_modes": tile.bucket_modes}
-    out["batched_ms_per_round"] = _median_ms(lambda: fed.round(0), rounds, 1)
-    fed.status()
-    fed.close()
+           "nnz": nnz, "forms": {}}
+
+    def measure(name, fed):
+        ms = _median_ms(lambda: fed.round(0), rounds, 1)
+        fed.status()
+        info = fed.info()
+        out["forms"][name] = {"ms_per_round": ms, "launches_per_round": info["launches_per_round"],
+                              "shape": {k: info[k] for k in ("form", "workgroups_per_client", "block", "lanes",
+                                                             "vec", "lds_modes", "bucket_modes")}}
+        log(f"fedadam: {name} {ms:.2f} ms per round ({info['form']}, {info['launches_per_round']} launches)")
+        fed.close()
+
+    measure("plain_atomic", Plain(clients, gd, U0, cfg, scatter="atomic"))
+    measure("plain_auto", Plain(clients, gd, U0, cfg, scatter="auto"))
+    for name, cands in (("persistent", "persistent"), ("bucketed", "bucketed")):
+        fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True,
+                      tile=FedTile(bucket_modes=0) if name == "persistent" else FedTile())
+        if tune:
+            pool = [c for c in autotune.fed_candidates(R, torch.float32, len(clients))
+                    if (c.bucket_modes == 0) == (cands == "persistent")]
+            autotune.tune_fedadam(fed, candidates=pool, rounds=1, warmup=1, use_cache=False)
+        measure(name, fed)
+    f = out["forms"]
+    best_plain = min(("plain_atomic", "plain_auto"), key=lambda k: f[k]["ms_per_round"])
+    best_batched = min(("persistent", "bucketed"), key=lambda k: f[k]["ms_per_round"])
+    out["best_plain"], out["best_batched"] = best_plain, best_batched
+    out["plain_ms_per_round"] = f[best_plain]["ms_per_round"]
+    out["batched_ms_per_round"] = f[best_batched]["ms_per_round"]
     out["speedup"] = out["plain_ms_per_round"] / out["batched_ms_per_round"]
+    out["speedup_same_scatter"] = {
+        "atomic (persistent vs plain_atomic)": f["plain_atomic"]["ms_per_round"] / f["persistent"]["ms_per_round"],
+        "row-bucketed (bucketed vs plain_auto)": f["plain_auto"]["ms_per_round"] / f["bucketed"]["ms_per_round"]}
     out["samples_per_round"] = 64 * 10 * (cfg.p + cfg.q)
     out["batched_samples_per_s"] = out["samples_per_round"] / (out["batched_ms_per_round"] * 1e-3)
-    log(f"fedadam: plain {out['plain_ms_per_round']:.2f} ms, batched {out['batched_ms_per_round']:.2f} ms per "
-        f"round -> {out['speedup']:.2f}x")
+    log(f"fedadam: best per-client {best_plain} {out['plain_ms_per_round']:.2f} ms, best batched {best_batched} "
+        f"{out['batched_ms_per_round']:.2f} ms per round -> {out['speedup']:.2f}x")
     return out
 
 
@@ -243,25 +291,57 @@ def run_autograd(dev, which: str, reps: int):
     return {"workload": desc, "ms_per_forward_backward": ms, "samples_per_s": s / (ms * 1e-3)}
 
 
-def run_cpu_baseline(data, A_init: np.ndarray, steps: int):
+def host_threads() -> int:
+    """Threads the host share allows: OMP_NUM_THREADS when set, else the CPU
+    count."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return n if n > 0 else (os.cpu_count() or 1)
+
+
+def run_cpu_baseline(data, A_init: np.ndarray, steps: int, par_steps: int):
+    """The FP64 oracle timed on the host over full steps of the same workload:
+    the serial checker (1 thread), then its timing-only OpenMP form with
+    thread-private gradients (the paper's CPU MTTKRP strategy) on every
+    thread the host share allows.  `value` is the all-threads figure."""
     import oracle
     log("cpu baseline: building the oracle's sorted index on the host")
     coords = data.coords.cpu().numpy()
     vals = data.vals.to(torch.float32).double().cpu().numpy()
     t_ora = oracle.SparseTensor(DIMS, coords, vals)
-    A = A_init.astype(np.float64).copy()
-    B = np.zeros_like(A)
-    Cm = np.zeros_like(A)
     ap = oracle.AdamParams(lr=1e-3, lower=0.0)
-    log(f"cpu baseline: timing {steps} full step(s) of {P + Q} samples")
+
+    def fresh():
+        A = A_init.astype(np.float64).copy()
+        return A, np.zeros_like(A), np.zeros_like(A)
+
+    A, B, Cm = fresh()
+    log(f"cpu baseline: timing {steps} full serial step(s) of {P + Q} samples")
     t0 = time.perf_counter()
     for k in range(steps):
         oracle.sgd_step(t_ora, RANK, A, B, Cm, k + 1, "poisson", P, Q, SAMPLE_SEED, k, ap)
-    dt = time.perf_counter() - t0
-    return {"value": steps * (P + Q) / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full step(s) of the same workload ({P}+{Q} stratified samples, "
-                      f"sampled gradient, Adam over all {A.size} parameters), serial FP64 C, "
-                      f"{dt:.1f} s"}
+    dt_serial = time.perf_counter() - t0
+    serial = steps * (P + Q) / dt_serial
+    threads = host_threads()
+    ps = oracle.ParallelStepper(t_ora, RANK, P, Q, threads)
+    A, B, Cm = fresh()
+    ps.step(A, B, Cm, 1, "poisson", SAMPLE_SEED, 0, ap)          # first touch of the workspaces
+    A, B, Cm = fresh()
+    log(f"cpu baseline: timing {par_steps} full step(s) on {threads} threads")
+    t0 = time.perf_counter()
+    for k in range(par_steps):
+        ps.step(A, B, Cm, k + 1, "poisson", SAMPLE_SEED, k, ap)
+    dt_par = time.perf_counter() - t0
+    par = par_steps * (P + Q) / dt_par
+    return {"value": par, "unit": "samples/s", "cores": ps.threads_used, "kind": "oracle",
+            "sample": f"{par_steps} full step(s) of the same workload ({P}+{Q} stratified samples, sampled "
+                      f"gradient, Adam over all {A.size} parameters), FP64 C, OpenMP over samples with "
+                      f"thread-private gradients on {ps.threads_used} threads, {dt_par:.1f} s; serially "
+                      f"{steps} step(s) in {dt_serial:.1f} s",
+            "serial": {"value": serial, "cores": 1, "steps": steps, "seconds": dt_serial},
+            "parallel_speedup": par / serial}
 
 
 def fused_experiment(dev, sizes, iters: int):
@@ -343,6 +423,99 @@ def hbm_resident(dev, nnz: int, steps: int, warmup: int):
             "frac": alg / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+ENGINE_CLOCK_HZ = 2.4e9      # MI355X peak engine clock
+CUS = 256
+
+
+def ceilings(dev, reps: int = 10):
+    """Measure the hardware ceilings of the sampled gradient's access patterns
+    (include/gcp_ceilings.h) on this device, and from them a lower bound on
+    the config-2 sampled-gradient call (2^20 + 2^20 samples, rank 32, three
+    modes, row-bucketed scatter) under this model:
+      sampling kernel: per sample one random record read (or probe) and three
+        dependent row gathers, at the dependent-gather rate, overlapped with
+        writing its 3 x 16-byte sort entries at the copy rate;
+      owner pass: per entry (3 per sample) two row gathers from a streamed
+        entry, at the streamed-gather rate, and 16 lanes' 64-bit LDS
+        compare-and-swap adds at the measured LDS rate, overlapped with
+        reading the entries back at the copy rate;
+      the two kernels run one after the other.
+    The bound is the sum over the two kernels of the slowest part of each."""
+    import ctypes as C
+    L = G.lib()
+    st = G._stream()
+    sink = torch.zeros(1 << 16, dtype=torch.int32, device=dev)
+
+    def timed(call):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        G._check(call(), "ceiling")
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record()
+            G._check(call(), "ceiling")
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    out = {"device": torch.cuda.get_device_name(0), "engine_clock_hz": ENGINE_CLOCK_HZ, "cus": CUS}
+    nrec = NNZ
+    rec = torch.randint(-2**31, 2**31 - 1, (nrec * 4,), dtype=torch.int32, device=dev)
+    nreads = 1 << 24
+    for inflight in (1, 4):
+        ms = timed(lambda: L.gcp_ceiling_random_reads(C.c_void_p(rec.data_ptr()), nrec, nreads, inflight, 512,
+                                                      C.c_void_p(sink.data_ptr()), st))
+        out[f"random_16B_reads_{inflight}_in_flight"] = {"per_s": nreads / (ms * 1e-3), "ms": ms, "n": nreads}
+    A = torch.rand(sum(DIMS) * RANK, dtype=torch.float32, device=dev)
+    dims3 = (C.c_int64 * 3)(*DIMS)
+    n = P + Q
+    for seq, name in ((0, "dependent_record_3_row_gathers"), (1, "streamed_record_3_row_gathers")):
+        best = None
+        for block in (512, 1024):
+            ms = timed(lambda: L.gcp_ceiling_dependent_gathers(C.c_void_p(rec.data_ptr()), nrec,
+                                                               C.c_void_p(A.data_ptr()), dims3, n, seq, block,
+                                                               C.c_void_p(sink.data_ptr()), st))
+            if best is None or ms < best[0]:
+                best = (ms, block)
+        out[name] = {"samples_per_s": n / (best[0] * 1e-3), "rows_per_s": 3 * n / (best[0] * 1e-3),
+                     "ms": best[0], "block": best[1], "n": n}
+    iters, block = 4096, 1024
+    grid = CUS * 2
+    ms = timed(lambda: L.gcp_ceiling_lds_cas(iters, block, grid, C.c_void_p(sink.data_ptr()), st))
+    lane_ops = grid * block * iters
+    out["lds_cas64"] = {"lane_ops_per_s": lane_ops / (ms * 1e-3),
+                        "wave_instr_per_clk_per_cu": lane_ops / 64 / (ms * 1e-3) / (CUS * ENGINE_CLOCK_HZ),
+                        "ms": ms}
+    Gr = torch.zeros(sum(DIMS) * RANK, dtype=torch.float32, device=dev)
+    nup = 1 << 22
+    ms = timed(lambda: L.gcp_ceiling_global_atomics(C.c_void_p(Gr.data_ptr()), sum(DIMS), nup, 512, st))
+    out["global_float_atomic_rows"] = {"requests_per_s": nup / (ms * 1e-3), "ms": ms, "n": nup}
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = timed(lambda: L.gcp_ceiling_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, st))
+    out["copy"] = {"gbs_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9, "ms": ms, "bytes": nbytes}
+    del rec, src, dst
+
+    # lower bound of the config-2 call
+    d, ent_bytes = 3, 16
+    copy_bps = out["copy"]["gbs_read_plus_write"] * 1e9
+    t_draw = n / out["dependent_record_3_row_gathers"]["samples_per_s"]
+    t_write = n * d * ent_bytes / copy_bps
+    t_owner_gather = n * d * 2 / out["streamed_record_3_row_gathers"]["rows_per_s"]
+    t_owner_cas = n * d * (RANK // 2) / out["lds_cas64"]["lane_ops_per_s"]
+    t_read = n * d * ent_bytes / copy_bps
+    parts_a = {"dependent record and row gathers": t_draw, "sort-entry writes": t_write}
+    parts_b = {"streamed-entry row gathers": t_owner_gather, "LDS compare-and-swap adds": t_owner_cas,
+               "sort-entry reads": t_read}
+    ka, kb = max(parts_a, key=parts_a.get), max(parts_b, key=parts_b.get)
+    out["config2_model_ms"] = {"sampling_kernel": {k: v * 1e3 for k, v in parts_a.items()},
+                               "owner_pass": {k: v * 1e3 for k, v in parts_b.items()}}
+    out["config2_call_lower_bound_ms"] = (parts_a[ka] + parts_b[kb]) * 1e3
+    out["binding"] = f"sampling kernel: {ka}; owner pass: {kb}"
+    out["commands"] = ["python3 bench.py --ceilings"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +523,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-par-steps", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the GCP-FedAdam round and autograd measurements")
     ap.add_argument("--fed-rounds", type=int, default=5)
@@ -358,6 +532,9 @@ def main():
                          "rocprofv3's FETCH_SIZE / WRITE_SIZE can be calibrated against known bytes")
     ap.add_argument("--fused-experiment", action="store_true",
                     help="only run the fused vs non-fused sampled-gradient comparison and print its JSON")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the sampled-gradient tile instead of taking the one the committed "
+                         "counter profile was taken at")
     ap.add_argument("--tile", default="",
                     help="fixed sampled-gradient tile instead of the autotuned one, as comma-separated "
                          "key=value pairs of gcp_tile fields (e.g. lanes=8,vec=4,block=256,bucket_block=1024); "
@@ -365,10 +542,16 @@ def main():
     ap.add_argument("--hbm-resident", action="store_true",
                     help="only run the HBM-resident-factor experiment (Amazon-shaped tensor) and print its JSON")
     ap.add_argument("--hbm-nnz", type=int, default=500_000_000)
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only measure the hardware ceilings of the sampled gradient's access patterns and the "
+                         "lower bound they put on the benchmark call; print their JSON")
     ap.add_argument("--fedadam-only", action="store_true",
                     help="only run the GCP-FedAdam comparison (per-client vs batched round, the library's "
                          "automatic launch shape, no autotuning) and print its JSON")
     args = ap.parse_args()
+    if args.ceilings:
+        print(json.dumps(ceilings(torch.device("cuda:0"))))
+        return
     if args.fedadam_only:
         print(json.dumps(run_fedadam(torch.device("cuda:0"), args.fed_rounds, tune=False)))
         return
@@ -397,36 +580,55 @@ def main():
     data, t, A = build_workload(dev)
     A0 = A.cpu().numpy().copy()
     sp0 = G.SampleParams("stratified", P, Q, seed=SAMPLE_SEED, step=0)
+    rec = traffic_record()
     if args.tile:
-        tile = parse_tile(args.tile)
-        log(f"fixed sampled-gradient tile: {tile}")
+        tile, tile_source = parse_tile(args.tile), "fixed"
+    elif args.autotune or not rec or "tile" not in rec:
+        tile, tile_source = autotune.tune_loss_grad(t, sp0, A, RANK, "poisson", reps=10), "autotuned"
     else:
-        tile = autotune.tune_loss_grad(t, sp0, A, RANK, "poisson", reps=10)
-        log(f"autotuned sampled-gradient tile: {tile}")
+        # the tile the committed counter profile was taken at (itself the
+        # autotuner's pick when it was profiled), so time and bytes pair up
+        tile, tile_source = G.Tile(**rec["tile"]), "profiled"
+    log(f"{tile_source} sampled-gradient tile: {tile}")
     log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
     wall, kms, loss_est, n_params = run_gpu(t, A, args.steps, args.warmup, tile)
     ms_per_step = 1e3 * wall / args.steps
     value = args.steps * (P + Q) / wall
     kmean = float(np.mean(kms))
     alg = algorithmic_bytes(3, RANK, P, Q)
-    achieved = alg / (kmean * 1e-3) / 1e9
-    traffic = measured_traffic()
-    traffic_gbs = traffic / (kmean * 1e-3) / 1e9 if traffic else None
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "traffic_gbs": round(traffic_gbs, 1) if traffic_gbs else None,
-            "traffic_frac": round(traffic_gbs / HBM_PEAK_GBS, 4) if traffic_gbs else None,
+    alg_gbs = alg / (kmean * 1e-3) / 1e9
+    # DRAM bytes per launch, only when the counters were taken on this kernel
+    # source at this very tile
+    traffic = rec.get("bytes_per_launch") if rec and rec.get("tile") == tile_dict(tile) else None
+    dram_gbs = traffic / (kmean * 1e-3) / 1e9 if traffic else None
+    roof = {"bound": "hbm",
+            "achieved": round(dram_gbs, 1) if dram_gbs else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(dram_gbs / HBM_PEAK_GBS, 4) if dram_gbs else None,
+            "traffic": traffic,
+            "achieved_from": "DRAM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated against a "
+                             "1 GiB copy; profiles/loss_grad_cfg2_traffic.json, same kernel source and tile) "
+                             "over the mean launch duration measured here with HIP events on the launch stream",
             "kernel": "gcp_loss_grad: k_loss_grad (sampling, model values, loss derivative, scatter or "
                       "row-block sort) + k_bucket_accum (row-block owner pass) when bucketed",
             "kernel_ms_mean": round(kmean, 5), "kernel_ms_median": round(float(np.median(kms)), 5),
-            "algorithmic_bytes_per_launch": alg}
-    log(f"step {ms_per_step:.4f} ms, {value:.4g} samples/s; loss_grad kernel {kmean:.4f} ms "
-        f"-> {achieved:.0f} GB/s algorithmic")
+            "algorithmic": {
+                "bytes_per_launch": alg, "rate_gbs": round(alg_gbs, 1),
+                "model": "1180 B per nonzero sample (int64 coordinates and value, 3 factor rows gathered, "
+                         "3 gradient rows read and written) and 1160 B per zero sample (one 8-byte probe "
+                         "instead), every access charged as if there were no cache; the 3 MB factor and "
+                         "gradient arrays live in the L2 and Infinity Cache here, so this rate is not an "
+                         "HBM figure and may exceed the HBM peak"}}
+    ceil = binding_ceiling(kmean)
+    if ceil:
+        roof["binding_ceiling"] = ceil
+    log(f"step {ms_per_step:.4f} ms, {value:.4g} samples/s; loss_grad kernel {kmean:.4f} ms; "
+        f"DRAM {dram_gbs or float('nan'):.0f} GB/s; algorithmic model {alg_gbs:.0f} GB/s")
     roof["tile"] = tile_dict(tile)
-    roof["tile_source"] = "fixed" if args.tile else "autotuned"
+    roof["tile_source"] = tile_source
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = run_cpu_baseline(data, A0, args.cpu_steps)
+        cpu = run_cpu_baseline(data, A0, args.cpu_steps, args.cpu_par_steps)
         log(f"cpu baseline {cpu['value']:.4g} samples/s")
     del data, t
     torch.cuda.empty_cache()

@@ -228,6 +228,36 @@ gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, const gcp_sa
                          const void* scale_dev, void* G_out, double* loss_out,
                          const gcp_tile* tile, hipStream_t stream);
 
+/* The non-fused sampled gradient (Sec. 3.1.2, the form the "Fused
+ * Sampling-MTTKRP" paragraph improves on): the sampling step computes every
+ * sample's model value and derivative and stores the sampled tensor Y~, and
+ * a separate MTTKRP reads Y~ and gathers the factor rows a second time.
+ *
+ * gcp_sample_y draws the samples of `sp` exactly as gcp_sample does, gathers
+ * their factor rows, and writes coords_out [n x d] (int64, device) and
+ * y_out [n] (tensor dtype, device) with y_s = w_s f'(x_s, m_s) (semi-
+ * stratified nonzero samples: w_s (f'(x_s, m_s) - f'(0, m_s))); loss_out
+ * (device double, nullable) receives F~ as in gcp_loss_grad.  Nothing is
+ * scattered; tile may set the lane shape and block (its scatter fields are
+ * ignored).  Errors as gcp_loss_grad; NULL coords_out or y_out is
+ * GCP_ERR_ARG. */
+gcp_status gcp_sample_y(gcp_tensor t, const gcp_sample_params* sp, const void* A, int R, gcp_loss loss,
+                        int64_t* coords_out, void* y_out, double* loss_out, const gcp_tile* tile,
+                        hipStream_t stream);
+
+/* Sampled MTTKRP of a given sampled tensor (eq. gcp-gradient with Y~):
+ *   G_k[i_k(s), :] += y_s prod_{j != k} A_j[i_j(s), :]   for every mode k,
+ * over the n entries of coords [n x d] (int64, device, each coordinate in
+ * range, else GCP_ERR_DATA through gcp_device_status) and y [n] (tensor
+ * dtype, device).  t supplies the dims and, when reserved, the row-bucketing
+ * workspace.  flags: GCP_ACCUMULATE (else G_out is overwritten) and
+ * GCP_SCALE_BY_DEV (every y times *scale_dev); tile as gcp_loss_grad (the
+ * same scatter strategies).  Duplicates are summed; the order of additions is
+ * unspecified. */
+gcp_status gcp_mttkrp(gcp_tensor t, int64_t n, const int64_t* coords, const void* y, const void* A, int R,
+                      unsigned flags, const void* scale_dev, void* G_out, const gcp_tile* tile,
+                      hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * call as gcp_loss_grad, with the same arguments, results and errors, except

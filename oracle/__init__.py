@@ -46,11 +46,12 @@ ORA_ERR_SAMPLING = -4
 
 
 def build(force: bool = False) -> str:
-    """Compile gcp_oracle.c with gcc (-O2, no fast-math) into liboracle.so."""
+    """Compile gcp_oracle.c with gcc (-O2, no fast-math; OpenMP for the
+    timing-only parallel step) into liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall",
-                               "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+                               "-fno-fast-math", "-fopenmp", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -93,6 +94,16 @@ def lib():
         L.ora_loss_grad_bound.argtypes = [C.c_int, i64p, C.c_int, f64p, C.c_int64, i64p, f64p, f64p,
                                           C.c_int, C.c_int64, C.c_double, f64p, f64p, i64p]
         L.ora_loss_grad_bound.restype = None
+        L.ora_omp_sgd_step.argtypes = [C.c_void_p, C.c_int, f64p, f64p, f64p, C.c_int64, C.c_int, C.c_int64,
+                                       C.c_int64, C.c_uint64, C.c_uint64, C.c_int64, C.c_double, C.c_double,
+                                       C.c_double, C.c_double, C.c_double, C.c_int, i64p, f64p, f64p, f64p, f64p,
+                                       C.POINTER(C.c_int)]
+        L.ora_omp_sgd_step.restype = C.c_int
+        L.ora_sample_derivatives.argtypes = [C.c_int, i64p, C.c_int, f64p, C.c_int64, i64p, f64p, f64p, C.c_int,
+                                             C.c_int64, f64p]
+        L.ora_sample_derivatives.restype = None
+        L.ora_mttkrp.argtypes = [C.c_int, i64p, C.c_int, f64p, C.c_int64, i64p, f64p, f64p]
+        L.ora_mttkrp.restype = None
         L.ora_adam.argtypes = [C.c_int64, f64p, f64p, f64p, f64p, C.c_int64, C.c_double,
                                C.c_double, C.c_double, C.c_double, C.c_double]
         L.ora_adam.restype = None
@@ -244,6 +255,33 @@ def loss_grad(dims, R: int, A, coords, x, w, loss, n_semi: int = 0):
     return G, float(F.value)
 
 
+def sample_derivatives(dims, R: int, A, coords, x, w, loss, n_semi: int = 0) -> np.ndarray:
+    """Values of the sampled tensor of the non-fused gradient (Sec. 3.1.2):
+    y_s = w_s f'(x_s, m_s), semi-stratified nonzeros w_s (f'(x_s,m_s) - f'(0,m_s))."""
+    dims = _i64(dims)
+    A = _f64(A).reshape(-1)
+    coords = _i64(coords).reshape(-1, int(dims.size))
+    x, w = _f64(x), _f64(w)
+    n = int(coords.shape[0])
+    y = np.zeros(n)
+    lib().ora_sample_derivatives(int(dims.size), _p(dims, C.c_int64), R, _p(A, C.c_double), n,
+                                 _p(coords, C.c_int64), _p(x, C.c_double), _p(w, C.c_double), _loss_id(loss),
+                                 int(n_semi), _p(y, C.c_double))
+    return y
+
+
+def mttkrp(dims, R: int, A, coords, y) -> np.ndarray:
+    """Sampled MTTKRP of a given sampled tensor: G_k[i_k, :] += y prod_{j != k} A_j[i_j, :]."""
+    dims = _i64(dims)
+    A = _f64(A).reshape(-1)
+    coords = _i64(coords).reshape(-1, int(dims.size))
+    y = _f64(y)
+    G = np.zeros(int(dims.sum()) * R)
+    lib().ora_mttkrp(int(dims.size), _p(dims, C.c_int64), R, _p(A, C.c_double), int(coords.shape[0]),
+                     _p(coords, C.c_int64), _p(y, C.c_double), _p(G, C.c_double))
+    return G
+
+
 U_F32 = 2.0 ** -24      # unit roundoff of binary32
 U_F64 = 2.0 ** -53      # unit roundoff of binary64
 
@@ -320,6 +358,37 @@ def sgd_step(t: SparseTensor, R: int, A, B, C_, adam_t: int, loss, p: int, q: in
     G, F = loss_grad(t.dims, R, A, coords, x, w, loss, n_semi=p if semi else 0)
     adam(A, G, B, C_, adam_t, ap.lr, ap.beta1, ap.beta2, ap.eps, ap.lower)
     return G, F
+
+
+class ParallelStepper:
+    """Timing-only OpenMP form of sgd_step (the paper's CPU MTTKRP with
+    thread-private gradients), for the benchmark's CPU baseline: same
+    samples and arithmetic, other order of the gradient's additions.  Holds
+    its sample and per-thread gradient workspaces."""
+
+    def __init__(self, t: SparseTensor, R: int, p: int, q: int, threads: int):
+        self.t, self.R, self.p, self.q, self.threads = t, R, p, q, int(threads)
+        n = p + q
+        rows = int(t.dims.sum())
+        self.coords = np.zeros((n, t.d), dtype=np.int64)
+        self.x = np.zeros(n)
+        self.w = np.zeros(n)
+        self.G_priv = np.zeros(self.threads * rows * R)
+        self.G = np.zeros(rows * R)
+        self.threads_used = 0
+
+    def step(self, A, B, C_, adam_t: int, loss, seed: int, step: int, ap: AdamParams, max_attempts: int = 64):
+        used = C.c_int(0)
+        st = lib().ora_omp_sgd_step(self.t._h, self.R, _p(A, C.c_double), _p(B, C.c_double), _p(C_, C.c_double),
+                                    int(adam_t), _loss_id(loss), self.p, self.q, C.c_uint64(seed),
+                                    C.c_uint64(step), int(max_attempts), ap.lr, ap.beta1, ap.beta2, ap.eps,
+                                    ap.lower, self.threads, _p(self.coords, C.c_int64), _p(self.x, C.c_double),
+                                    _p(self.w, C.c_double), _p(self.G_priv, C.c_double), _p(self.G, C.c_double),
+                                    C.byref(used))
+        if st != ORA_OK:
+            raise OracleError(st, "ora_omp_sgd_step")
+        self.threads_used = used.value
+        return self.G
 
 
 @dataclass

@@ -351,6 +351,41 @@ void ora_loss_grad(int d, const int64_t* dims, int R, const double* A, int64_t n
     if (F) *F = Fsum;
 }
 
+/* The two steps of the non-fused sampled gradient (Sec. 3.1.2), written out
+ * on their own: the derivative values of the sampled tensor,
+ *   y_s = w_s f'(x_s, m_s)   (s < n_semi: w_s (f'(x_s, m_s) - f'(0, m_s))),
+ * and the sampled MTTKRP of a given sampled tensor (coords, y),
+ *   G_k[i_k(s), r] += y_s prod_{j != k} A_j[i_j(s), r]   (G overwritten). */
+void ora_sample_derivatives(int d, const int64_t* dims, int R, const double* A, int64_t n, const int64_t* coords,
+                            const double* x, const double* w, int loss, int64_t n_semi, double* y)
+{
+    for (int64_t s = 0; s < n; ++s) {
+        const double m = ora_model_value(d, dims, R, A, coords + s * d);
+        y[s] = w[s] * ora_df(loss, x[s], m);
+        if (s < n_semi) y[s] = w[s] * (ora_df(loss, x[s], m) - ora_df(loss, 0.0, m));
+    }
+}
+
+void ora_mttkrp(int d, const int64_t* dims, int R, const double* A, int64_t n, const int64_t* coords,
+                const double* y, double* G)
+{
+    int64_t rowoff[9];
+    ora_rowoff(d, dims, rowoff);
+    memset(G, 0, sizeof(double) * (size_t)(rowoff[d] * R));
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t* idx = coords + s * d;
+        for (int k = 0; k < d; ++k) {
+            double* g = G + (rowoff[k] + idx[k]) * R;
+            for (int r = 0; r < R; ++r) {
+                double prod = y[s];
+                for (int j = 0; j < d; ++j)
+                    if (j != k) prod *= A[(rowoff[j] + idx[j]) * R + r];
+                g[r] += prod;
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Rounding-error bound of a sampled gradient computed in a floating-point   */
 /* format with unit roundoff u (2^-24 for binary32, 2^-53 for binary64),     */
@@ -478,4 +513,107 @@ void ora_adam(int64_t n, double* A, const double* G, double* B, double* C, int64
         double chat = C[i] / c2;
         A[i] = fmax(A[i] - lr * (bhat / sqrt(chat + eps)), lower);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Timing-only parallel step, for the CPU baseline of the benchmark (not a   */
+/* checker: the parity tests use the serial functions above).  One           */
+/* synchronous GCP-SGD/Adam iteration -- stratified samples, sampled         */
+/* gradient, Adam -- with the paper's CPU strategy for the MTTKRP (Sec.      */
+/* 3.1.2, thread privatization): OpenMP threads split the samples, each      */
+/* accumulates into its own copy of G, and the copies are summed.  Same      */
+/* samples and arithmetic as the serial path; only the order of the          */
+/* gradient's additions differs.                                             */
+/*   coords_ws [(p+q) x d], x_ws, w_ws [p+q]: sample workspace;              */
+/*   G_priv [nthreads x rows x R], G [rows x R]: gradient workspace.         */
+/* Returns ORA_OK, ORA_ERR_ARG or ORA_ERR_SAMPLING; *threads_used gets the   */
+/* size of the thread team.                                                  */
+/* ------------------------------------------------------------------------ */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int ora_omp_sgd_step(const ora_tensor* t, int R, double* A, double* B, double* C, int64_t adam_t,
+                     int loss, int64_t p, int64_t q, uint64_t seed, uint64_t step, int64_t max_attempts,
+                     double lr, double beta1, double beta2, double eps, double lower, int nthreads,
+                     int64_t* coords_ws, double* x_ws, double* w_ws, double* G_priv, double* G,
+                     int* threads_used)
+{
+    const int d = t->d;
+    const int64_t N = t->nnz;
+    const uint64_t M = ora_cell_count_u(d, t->dims);
+    if (p < 0 || q < 0 || (p > 0 && N == 0) || (q > 0 && (uint64_t)N >= M) || nthreads < 1) return ORA_ERR_ARG;
+    const double w_nz = p > 0 ? (double)N / (double)p : 0.0;
+    const double w_z = q > 0 ? (double)(M - (uint64_t)N) / (double)q : 0.0;
+    const int64_t n = p + q;
+    int64_t rowoff[9];
+    ora_rowoff(d, t->dims, rowoff);
+    const int64_t elems = rowoff[d] * R;
+    const double c1 = 1.0 - pow(beta1, (double)adam_t);
+    const double c2 = 1.0 - pow(beta2, (double)adam_t);
+    int status = ORA_OK;
+    int team = 1;
+    #pragma omp parallel num_threads(nthreads)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+        #pragma omp single
+        team = omp_get_num_threads();
+#endif
+        const uint64_t key[2] = {seed, 0};
+        #pragma omp for schedule(static)
+        for (int64_t s = 0; s < p; ++s) {
+            uint64_t ctr[4] = {(uint64_t)s, step, ORA_STREAM_NONZERO, 0};
+            uint64_t out[4];
+            ora_philox4x64_10(ctr, key, out);
+            const int64_t j = (int64_t)ora_range(out[0], (uint64_t)N);
+            for (int k = 0; k < d; ++k) coords_ws[s * d + k] = t->coords[j * d + k];
+            x_ws[s] = t->vals[j];
+            w_ws[s] = w_nz;
+        }
+        #pragma omp for schedule(dynamic, 1024)
+        for (int64_t s = 0; s < q; ++s) {
+            int64_t* idx = coords_ws + (p + s) * d;
+            int found = 0;
+            for (int64_t a = 0; a < max_attempts; ++a) {
+                ora_draw_cell(d, t->dims, seed, 0, (uint64_t)s, step, ORA_STREAM_ZERO, (uint64_t)a, idx);
+                if (ora_find(t, idx) < 0) { found = 1; break; }
+            }
+            if (!found) {
+                #pragma omp atomic write
+                status = ORA_ERR_SAMPLING;
+            }
+            x_ws[p + s] = 0.0;
+            w_ws[p + s] = w_z;
+        }
+        double* Gt = G_priv + (int64_t)tid * elems;
+        memset(Gt, 0, sizeof(double) * (size_t)elems);
+        #pragma omp for schedule(static)
+        for (int64_t s = 0; s < n; ++s) {
+            const int64_t* idx = coords_ws + s * d;
+            const double m = ora_model_value(d, t->dims, R, A, idx);
+            const double y = w_ws[s] * ora_df(loss, x_ws[s], m);
+            for (int k = 0; k < d; ++k) {
+                double* g = Gt + (rowoff[k] + idx[k]) * R;
+                for (int r = 0; r < R; ++r) {
+                    double prod = y;
+                    for (int nn = 0; nn < d; ++nn)
+                        if (nn != k) prod *= A[(rowoff[nn] + idx[nn]) * R + r];
+                    g[r] += prod;
+                }
+            }
+        }
+        #pragma omp for schedule(static)
+        for (int64_t e = 0; e < elems; ++e) {
+            double g = 0.0;
+            for (int th = 0; th < team; ++th) g += G_priv[(int64_t)th * elems + e];
+            G[e] = g;
+            B[e] = beta1 * B[e] + (1.0 - beta1) * g;
+            C[e] = beta2 * C[e] + (1.0 - beta2) * g * g;
+            A[e] = fmax(A[e] - lr * ((B[e] / c1) / sqrt(C[e] / c2 + eps)), lower);
+        }
+    }
+    *threads_used = team;
+    return status;
 }

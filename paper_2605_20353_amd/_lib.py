@@ -84,6 +84,14 @@ def _declare(L):
         "gcp_loss_grad_noalloc": ([vp, C.POINTER(gcp_sample_params), C.POINTER(gcp_samples), vp, C.c_int,
                                    C.c_int, u, vp, vp, vp, C.POINTER(gcp_tile), vp], C.c_int),
         "gcp_noalloc_scratch_bytes": ([], i64),
+        "gcp_sample_y": ([vp, C.POINTER(gcp_sample_params), vp, C.c_int, C.c_int, vp, vp, vp, C.POINTER(gcp_tile),
+                          vp], C.c_int),
+        "gcp_mttkrp": ([vp, i64, vp, vp, vp, C.c_int, u, vp, vp, C.POINTER(gcp_tile), vp], C.c_int),
+        "gcp_ceiling_random_reads": ([vp, i64, i64, C.c_int, C.c_int, vp, vp], C.c_int),
+        "gcp_ceiling_dependent_gathers": ([vp, i64, vp, C.POINTER(i64), i64, C.c_int, C.c_int, vp, vp], C.c_int),
+        "gcp_ceiling_lds_cas": ([C.c_int, C.c_int, C.c_int, vp, vp], C.c_int),
+        "gcp_ceiling_global_atomics": ([vp, i64, i64, C.c_int, vp], C.c_int),
+        "gcp_ceiling_copy": ([vp, vp, i64, vp], C.c_int),
         "gcp_adam_step": ([vp, vp, vp, vp, i64, C.c_int, i64, d_, d_, d_, d_, d_, u, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -110,10 +118,16 @@ def lib():
 
 
 def header_functions() -> list:
-    """Names of the functions declared in include/gcp.h."""
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(gcp_[a-z0-9_]+)\s*\(", txt)))
+    """Names of the functions declared in the headers under include/."""
+    names = set()
+    inc = os.path.dirname(HEADER)
+    for h in sorted(os.listdir(inc)):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(inc, h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names.update(re.findall(r"\b(gcp_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def _check(code: int, fn: str):
@@ -351,6 +365,47 @@ def gcp_loss_grad(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, lo
                               _stream(stream)), fn)
     del keep
     return G, loss_out
+
+
+def gcp_sample_y(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, loss: str, coords=None, y=None,
+                 loss_out: torch.Tensor | None = None, tile: Tile | None = None, stream=None):
+    """Non-fused sampling step: the sampled tensor (coords [n, d] int64, y [n])
+    with y = w f'(x, m) of the model A.  Returns (coords, y, loss_out)."""
+    _require_cuda(A, coords, y, loss_out)
+    if A.dtype != t.dtype or not A.is_contiguous() or A.numel() != t.model_rows * R:
+        raise ValueError("A must be a contiguous model of the tensor's dtype and shape")
+    n = sp.n
+    if coords is None:
+        coords = torch.empty(n, t.d, dtype=torch.int64, device=A.device)
+    if y is None:
+        y = torch.empty(n, dtype=t.dtype, device=A.device)
+    spc = sp.c()
+    tl = tile.c() if tile is not None else None
+    _check(lib().gcp_sample_y(t.handle, C.byref(spc), _ptr(A), int(R), LOSSES[loss], _ptr(coords), _ptr(y),
+                              _ptr(loss_out), C.byref(tl) if tl is not None else None, _stream(stream)),
+           "gcp_sample_y")
+    return coords, y, loss_out
+
+
+def gcp_mttkrp(t: SparseTensor, coords: torch.Tensor, y: torch.Tensor, A: torch.Tensor, R: int,
+               G: torch.Tensor | None = None, accumulate: bool = False, scale: torch.Tensor | None = None,
+               tile: Tile | None = None, stream=None) -> torch.Tensor:
+    """Sampled MTTKRP of a given sampled tensor (coords [n, d], values y)."""
+    _require_cuda(coords, y, A, G, scale)
+    n = int(y.numel())
+    coords = coords.to(torch.int64).contiguous()
+    y = y.contiguous()
+    if coords.shape != (n, t.d) or y.dtype != A.dtype or A.dtype != t.dtype:
+        raise ValueError("coords must be [n, d] int64 and y of the model's dtype")
+    if G is None:
+        G = torch.empty_like(A)
+    flags = GCP_ACCUMULATE if accumulate else 0
+    if scale is not None:
+        flags |= GCP_SCALE_BY_DEV
+    tl = tile.c() if tile is not None else None
+    _check(lib().gcp_mttkrp(t.handle, n, _ptr(coords), _ptr(y), _ptr(A), int(R), flags, _ptr(scale), _ptr(G),
+                            C.byref(tl) if tl is not None else None, _stream(stream)), "gcp_mttkrp")
+    return G
 
 
 def gcp_loss_grad_noalloc(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, loss: str,

@@ -295,6 +295,11 @@ __device__ __forceinline__ bool table_contains(const uint64_t* __restrict__ tabl
 
 // ------------------------------------------------------------------ losses --
 
+// Internal loss code of the sampled MTTKRP over a given sampled tensor: its
+// values are already the derivative values, so y = w x (the kernels take
+// that branch at compile time).
+constexpr int kLossGivenValues = 3;
+
 template <typename T>
 __device__ __forceinline__ T loss_df(int loss, T x, T m)
 {
@@ -348,11 +353,20 @@ struct LGWorkspace {
     int64_t scratch_bytes = 0;  // > 0: fixed scratch region of this size
 };
 
+// The non-fused forms of the sampled gradient (Sec. 3.1.2): the sampling
+// kernel may write the sampled tensor Y~ -- each sample's coordinates and its
+// derivative value y = w f'(x, m) -- instead of scattering, and the MTTKRP
+// may read such a tensor (its values are then y, loss kLossGivenValues).
+struct LGOutputs {
+    void* y_out = nullptr;          // [n] tensor dtype
+    int64_t* coords_out = nullptr;  // [n x d]
+};
+
 // gcp_loss_grad with an explicit bucketed-scatter workspace (the argument
 // checks and launches of loss_grad.hip).
 gcp_status loss_grad_with_workspace(gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
                                     const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
                                     void* G_out, double* loss_out, const gcp_tile* tile, const LGWorkspace& ws,
-                                    hipStream_t stream);
+                                    hipStream_t stream, const LGOutputs* xo = nullptr);
 
 }  // namespace gcp

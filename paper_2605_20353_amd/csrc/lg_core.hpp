@@ -13,7 +13,7 @@ struct LGParams {
     SampleCtx<T> sc;
     int64_t n;            // samples p + q
     int64_t nchunks;      // ceil(n / 64)
-    const int64_t* m_coords;  // materialised list (SRC = 1)
+    const int64_t* m_coords;  // materialised list (SRC = 1, 3)
     const T* m_x;
     const T* m_w;
     const T* A;
@@ -24,6 +24,8 @@ struct LGParams {
     int semi;             // semi-stratified: samples s < p get f'(x,m) - f'(0,m)
     const T* scale;       // nullable device scalar
     double* loss_out;     // nullable
+    T* y_out;             // SRC = 2: each sample's y (the sampled tensor's values) ...
+    int64_t* c_out;       // ... and coordinates [n x d], written instead of scattering
     int64_t rowoff[kMaxModes];
     uint32_t lds_mask;    // modes accumulated in LDS
     int64_t lds_off[kMaxModes];
@@ -246,6 +248,13 @@ constexpr int owner_in_flight()
 // sample, stage it in the wave's LDS slice) and phase 2 (LANES lanes per
 // sample: gather rows, model value, loss derivative, scatter).  Shared by the
 // sampled-gradient kernel and the batched GCP-FedAdam kernel.
+//   SRC = 0  draw the samples (the fused sampled gradient);
+//   SRC = 1  read a materialised sample list (coordinates, x, w);
+//   SRC = 2  draw the samples and write the sampled tensor (coordinates and
+//            y = w f'(x, m)) instead of scattering: the sampling step of the
+//            non-fused gradient;
+//   SRC = 3  read a sampled tensor whose values are already y (w = 1 unless a
+//            weight list is given): the MTTKRP step of the non-fused gradient.
 template <typename T, int D, int LANES, int VEC, int SRC>
 __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, int lane, uint64_t* skey, T* sx,
                                          T* sw, T* priv, uint64_t* bkey, T* by, int64_t block_s0, bool tiled,
@@ -265,7 +274,7 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
         uint64_t key = 0;
         T x = T(0), w = T(0);
         if (s < P.n) {
-            if constexpr (SRC == 0) {
+            if constexpr (SRC == 0 || SRC == 2) {
                 draw_sample<T, D>(P.sc, step, s, key, x, w);
             } else {
                 bool ok = true;
@@ -278,7 +287,7 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
                     }
                 }
                 x = P.m_x[s];
-                w = P.m_w[s];
+                w = P.m_w ? P.m_w[s] : T(1);
                 if (!ok) {
                     atomicOr(P.sc.status, kStatusData);
                     key = 0;
@@ -340,13 +349,30 @@ __device__ __forceinline__ void lg_chunk(const LGParams<T>& P, int64_t chunk, in
             const int64_t s = s0 + slot;
             if (s >= P.n) continue;
             const T x = sx[slot], w = sw[slot];
-            const bool semi_nz = P.semi && s < P.sc.p;
-            T y = w * loss_df<T>(P.loss, x, m[u]);
-            if (semi_nz) y -= w * loss_df<T>(P.loss, T(0), m[u]);
-            if (P.loss_out && cl == 0) {
-                T l = w * loss_f<T>(P.loss, x, m[u]);
-                if (semi_nz) l -= w * loss_f<T>(P.loss, T(0), m[u]);
-                lacc += (double)l;
+            T y;
+            if constexpr (SRC == 3) {
+                y = w * x;
+            } else {
+                const bool semi_nz = P.semi && s < P.sc.p;
+                y = w * loss_df<T>(P.loss, x, m[u]);
+                if (semi_nz) y -= w * loss_df<T>(P.loss, T(0), m[u]);
+                if (P.loss_out && cl == 0) {
+                    T l = w * loss_f<T>(P.loss, x, m[u]);
+                    if (semi_nz) l -= w * loss_f<T>(P.loss, T(0), m[u]);
+                    lacc += (double)l;
+                }
+            }
+            if constexpr (SRC == 2) {
+                // the sampled tensor Y~ goes to memory; nothing is scattered
+                if (cl == 0) {
+                    uint32_t ci[DM];
+                    unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < dd) P.c_out[s * dd + k] = (int64_t)ci[k];
+                    P.y_out[s] = y;
+                }
+                continue;
             }
             if (P.loss_only) continue;
             y *= scale;

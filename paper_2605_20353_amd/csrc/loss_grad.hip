@@ -29,157 +29,9 @@
 //     bounds the atomic strategy at large sample counts.
 #include <cmath>
 
-#include "lg_core.hpp"
+#include "lg_kernels.hpp"
 
 namespace gcp {
-
-template <typename T, int D, int LANES, int VEC, int SRC>
-__global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
-{
-    constexpr int DM = D > 0 ? D : kMaxModes;
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int nwaves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint64_t* skey = reinterpret_cast<uint64_t*>(smem) + wave * 64;
-    T* sx = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * 8) + wave * 64;
-    T* sw = reinterpret_cast<T*>(smem + (size_t)nwaves * 64 * (8 + sizeof(T))) + wave * 64;
-    T* priv = reinterpret_cast<T*>(smem + P.staging_bytes);
-    // bucketed scatter staging: the workgroup's samples in order
-    uint64_t* bkey = reinterpret_cast<uint64_t*>(smem + P.bucket_lds);
-    T* by = reinterpret_cast<T*>(smem + P.bucket_lds + (size_t)P.spb * 8);
-    int* bcnt = reinterpret_cast<int*>(smem + P.bucket_lds + (size_t)P.spb * (8 + sizeof(T)));
-    int* boff = bcnt + P.nb;
-
-    if (P.lds_mask) {
-        for (int64_t e = threadIdx.x; e < P.lds_elems; e += blockDim.x) priv[e] = T(0);
-        __syncthreads();
-    }
-    const int dd = D > 0 ? D : P.sc.d;
-    const int R = P.R;
-    const T scale = P.scale ? *P.scale : T(1);
-    const bool tiled = P.bucket_mask != 0;
-    const int64_t block_s0 = tiled ? (int64_t)blockIdx.x * P.spb : 0;
-    double lacc = 0.0;
-
-    // tiled launches give workgroup j the chunks of samples [j*spb, (j+1)*spb)
-    int64_t chunk, chunk_end, chunk_step;
-    if (tiled) {
-        chunk = block_s0 / 64 + wave;
-        chunk_end = std::min<int64_t>(P.nchunks, (block_s0 + P.spb) / 64);
-        chunk_step = nwaves;
-    } else {
-        chunk = (int64_t)blockIdx.x * nwaves + wave;
-        chunk_end = P.nchunks;
-        chunk_step = (int64_t)gridDim.x * nwaves;
-    }
-
-    for (; chunk < chunk_end; chunk += chunk_step) {
-        lg_chunk<T, D, LANES, VEC, SRC>(P, chunk, lane, skey, sx, sw, priv, bkey, by, block_s0, tiled, scale,
-                                        lacc, P.sc.step);
-    }
-
-    if (P.loss_out) {
-        for (int off = 32; off >= 1; off >>= 1) lacc += xor_shfl(lacc, off);
-        if (lane == 0 && lacc != 0.0) atomicAdd(P.loss_out, lacc);
-    }
-    if (P.lds_mask) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            if (k < dd && ((P.lds_mask >> k) & 1u)) {
-                const int64_t rows = P.sc.L.dims[k];
-                T* dst = P.G + P.rowoff[k] * R;
-                const T* src = priv + P.lds_off[k];
-                for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) {
-                    const T v = src[e];
-                    if (v != T(0)) global_add(dst + e, v);
-                }
-            }
-        }
-    }
-    if (tiled && !P.loss_only)
-        bucket_write_out<T, D>(P, blockIdx.x, (int)std::min<int64_t>(P.spb, P.n - block_s0), bkey, by, bcnt, boff);
-}
-
-// Row-block owner pass of the bucketed scatter.  Workgroup (b, split) owns
-// rows [r0, r0 + 2^br_shift) of bucket b's mode k and reads the segments of
-// workgroups [j0, j1) of the sampling launch: per entry it gathers the other
-// modes' rows, forms y prod_{n != k} A_n[i_n, :] and adds it to the LDS copy
-// of its rows; the block is flushed to G once.
-template <typename T, int D, int LANES, int VEC>
-__global__ void __launch_bounds__(1024) k_bucket_accum(const LGParams<T> P)
-{
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    T* part = reinterpret_cast<T*>(smem);
-    const int R = P.R;
-    const int dd = D > 0 ? D : P.sc.d;
-
-    // the mode whose workgroup range holds this workgroup (ranges of modes
-    // that are not bucketed are empty), then its row block and split
-    int k = 0;
-    for (int kk = 0; kk < dd; ++kk)
-        if (P.bwg_base[kk] <= (int64_t)blockIdx.x && (int64_t)blockIdx.x < P.bwg_base[kk + 1]) k = kk;
-    const int splits = P.bsplits[k];
-    const int64_t local = (int64_t)blockIdx.x - P.bwg_base[k];
-    const int b = P.bucket_base[k] + (int)(local / splits);
-    const int split = (int)(local % splits);
-    const int64_t r0 = (int64_t)(b - P.bucket_base[k]) << P.br_shift;
-    const int64_t rows = std::min<int64_t>((int64_t)1 << P.br_shift, P.sc.L.dims[k] - r0);
-    // whole segments per workgroup (the host makes it a multiple of the
-    // waves per workgroup); the last split takes the remainder
-    const int64_t j0 = (int64_t)split * P.bsegs[k];
-    const int64_t j1 = std::min<int64_t>(P.nblocks, j0 + P.bsegs[k]);
-    int* seg_cnt = reinterpret_cast<int*>(smem + (((size_t)rows * R * sizeof(T) + 15) & ~(size_t)15));
-    bucket_accumulate<T, D, LANES, VEC>(P, k, b, r0, rows, j0, j1, part, seg_cnt);
-    __syncthreads();
-    T* dst = P.G + (P.rowoff[k] + r0) * R;
-    for (int64_t e = threadIdx.x; e < rows * R; e += blockDim.x) {
-        const T v = part[e];
-        if (v != T(0)) global_add(dst + e, v);
-    }
-}
-
-template <typename T>
-__global__ void k_zero(T* __restrict__ p, int64_t n, double* __restrict__ loss_out)
-{
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i0 == 0 && loss_out) *loss_out = 0.0;
-    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = T(0);
-}
-
-template <typename T>
-using LGKernel = void (*)(const LGParams<T>);
-template <typename T>
-using BAKernel = void (*)(const LGParams<T>);
-
-// (lanes, vec) shapes built for each dtype
-#define GCP_LG_SHAPES_F32(X) \
-    X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(64, 2) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4)
-#define GCP_LG_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(64, 2) X(64, 4)
-
-// The general-order (D = 0) float64 kernel with 64 lanes of one column is not
-// built: this toolchain fails to generate code for it on gfx950.  Even R uses
-// 32 lanes of two columns instead.
-template <typename T, int D, int LN, int VC>
-constexpr bool shape_built()
-{
-    return !(D == 0 && sizeof(T) == 8 && LN == 64 && VC == 1);
-}
-
-template <typename T, int D, int SRC>
-static LGKernel<T> pick_shape(int lanes, int vec)
-{
-#define GCP_CASE(LN, VC)                                          \
-    if constexpr (shape_built<T, D, LN, VC>())                    \
-        if (lanes == LN && vec == VC) return k_loss_grad<T, D, LN, VC, SRC>;
-    if constexpr (sizeof(T) == 4) {
-        GCP_LG_SHAPES_F32(GCP_CASE)
-    } else {
-        GCP_LG_SHAPES_F64(GCP_CASE)
-    }
-#undef GCP_CASE
-    return nullptr;
-}
 
 template <typename T, int D>
 static BAKernel<T> pick_bucket_shape(int lanes, int vec)
@@ -198,6 +50,7 @@ static BAKernel<T> pick_bucket_shape(int lanes, int vec)
 template <typename T>
 static LGKernel<T> pick_kernel(int d, int src, int lanes, int vec)
 {
+    if (src >= 2) return pick_kernel_nonfused<T>(d, src, lanes, vec);
     if (src == 0) {
         if (d == 3) return pick_shape<T, 3, 0>(lanes, vec);
         if (d == 4) return pick_shape<T, 4, 0>(lanes, vec);
@@ -259,24 +112,29 @@ template <typename T>
 static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
                                    const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
                                    void* G_out, double* loss_out, const gcp_tile* tile, const LGWorkspace& ws,
-                                   hipStream_t stream)
+                                   hipStream_t stream, const LGOutputs* xo)
 {
     LGParams<T> P{};
     int64_t n = 0;
     gcp_status st = make_sample_ctx<T>(t, sp, P.sc, n);
     if (st != GCP_OK) return st;
-    const bool loss_only = (flags & GCP_LOSS_ONLY) != 0;
+    const bool write_y = xo && xo->y_out;
+    const bool loss_only = (flags & GCP_LOSS_ONLY) != 0 || write_y;
+    const bool given_values = (int)loss == kLossGivenValues;
     const bool accumulate = (flags & GCP_ACCUMULATE) != 0;
     if (flags & ~(GCP_LOSS_ONLY | GCP_ACCUMULATE | GCP_SCALE_BY_DEV))
         return set_error(GCP_ERR_ARG, "unknown flags 0x%x", flags);
     if (!A) return set_error(GCP_ERR_ARG, "A is NULL");
     if (R < 1 || R > 256) return set_error(GCP_ERR_ARG, "R = %d outside [1, 256]", R);
-    if (loss < GCP_LOSS_GAUSSIAN || loss > GCP_LOSS_BERNOULLI_LOGIT) return set_error(GCP_ERR_ARG, "loss %d", (int)loss);
+    if ((loss < GCP_LOSS_GAUSSIAN || loss > GCP_LOSS_BERNOULLI_LOGIT) && !(given_values && smp))
+        return set_error(GCP_ERR_ARG, "loss %d", (int)loss);
     if (!loss_only && !G_out) return set_error(GCP_ERR_ARG, "G_out is NULL");
     if ((flags & GCP_SCALE_BY_DEV) && !scale_dev) return set_error(GCP_ERR_ARG, "scale_dev is NULL");
-    if (loss_only && !loss_out) return set_error(GCP_ERR_ARG, "GCP_LOSS_ONLY without loss_out");
-    if (smp && (!smp->coords || !smp->x || !smp->w) && n > 0)
+    if (loss_only && !loss_out && !write_y) return set_error(GCP_ERR_ARG, "GCP_LOSS_ONLY without loss_out");
+    if (write_y && (smp || !xo->coords_out)) return set_error(GCP_ERR_ARG, "sampled-tensor output needs coords_out");
+    if (smp && (!smp->coords || !smp->x || (!smp->w && !given_values)) && n > 0)
         return set_error(GCP_ERR_ARG, "materialised sample list has a NULL array");
+    if (given_values && loss_out) return set_error(GCP_ERR_ARG, "the MTTKRP of a given sampled tensor has no objective");
 
     const int d = t->d;
     const int cus = device_cu_count(t->device);
@@ -380,7 +238,7 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     }
     if (R % vec != 0) return set_error(GCP_ERR_ARG, "vec = %d does not divide R = %d", vec, R);
     if (lanes * vec < R) return set_error(GCP_ERR_ARG, "lanes*vec = %d < R = %d", lanes * vec, R);
-    const int src = smp ? 1 : 0;
+    const int src = write_y ? 2 : smp ? (given_values ? 3 : 1) : 0;
     if (sizeof(T) == 8 && kernel_order(t) == 0 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
         lanes = 32;
         vec = 2;
@@ -434,6 +292,10 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     P.semi = sp->kind == GCP_SAMPLE_SEMI_STRATIFIED;
     P.scale = (flags & GCP_SCALE_BY_DEV) ? (const T*)scale_dev : nullptr;
     P.loss_out = loss_out;
+    if (write_y) {
+        P.y_out = (T*)xo->y_out;
+        P.c_out = xo->coords_out;
+    }
     for (int k = 0; k < kMaxModes; ++k) P.rowoff[k] = k < d ? t->rowoff[k] : t->rowoff[d];
     P.lds_mask = lds_mask;
     P.lds_elems = lds_elems;
@@ -516,11 +378,23 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
 gcp_status loss_grad_with_workspace(gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
                                     const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
                                     void* G_out, double* loss_out, const gcp_tile* tile, const LGWorkspace& ws,
-                                    hipStream_t stream)
+                                    hipStream_t stream, const LGOutputs* xo)
 {
     if (t->dt == GCP_F32)
-        return launch_loss_grad<float>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream);
-    return launch_loss_grad<double>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream);
+        return launch_loss_grad<float>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream,
+                                       xo);
+    return launch_loss_grad<double>(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream,
+                                    xo);
+}
+
+static LGWorkspace reserved_workspace(const gcp_tensor_s* t)
+{
+    LGWorkspace ws;
+    ws.base = t->ws;
+    ws.entries = t->ws_entries;
+    ws.hist = t->ws_hist;
+    ws.max_samples = t->ws_max_samples;
+    return ws;
 }
 
 }  // namespace gcp
@@ -531,10 +405,40 @@ extern "C" gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, c
 {
     gcp::clear_error();
     if (!t) return gcp::set_error(GCP_ERR_ARG, "tensor is NULL");
-    gcp::LGWorkspace ws;
-    ws.base = t->ws;
-    ws.entries = t->ws_entries;
-    ws.hist = t->ws_hist;
-    ws.max_samples = t->ws_max_samples;
-    return gcp::loss_grad_with_workspace(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, ws, stream);
+    return gcp::loss_grad_with_workspace(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile,
+                                         gcp::reserved_workspace(t), stream);
+}
+
+extern "C" gcp_status gcp_sample_y(gcp_tensor t, const gcp_sample_params* sp, const void* A, int R, gcp_loss loss,
+                                   int64_t* coords_out, void* y_out, double* loss_out, const gcp_tile* tile,
+                                   hipStream_t stream)
+{
+    gcp::clear_error();
+    if (!t) return gcp::set_error(GCP_ERR_ARG, "tensor is NULL");
+    if (!y_out || !coords_out) return gcp::set_error(GCP_ERR_ARG, "coords_out or y_out is NULL");
+    gcp::LGOutputs xo;
+    xo.y_out = y_out;
+    xo.coords_out = coords_out;
+    gcp_tile tl = tile ? *tile : gcp_tile{};
+    tl.lds_modes = 0;               // this kernel scatters nothing
+    tl.bucket_modes = 0;
+    return gcp::loss_grad_with_workspace(t, sp, nullptr, A, R, loss, 0u, nullptr, nullptr, loss_out, &tl,
+                                         gcp::LGWorkspace{}, stream, &xo);
+}
+
+extern "C" gcp_status gcp_mttkrp(gcp_tensor t, int64_t n, const int64_t* coords, const void* y, const void* A,
+                                 int R, unsigned flags, const void* scale_dev, void* G_out, const gcp_tile* tile,
+                                 hipStream_t stream)
+{
+    gcp::clear_error();
+    if (!t) return gcp::set_error(GCP_ERR_ARG, "tensor is NULL");
+    if (n < 0) return gcp::set_error(GCP_ERR_ARG, "n < 0");
+    if (flags & GCP_LOSS_ONLY) return gcp::set_error(GCP_ERR_ARG, "GCP_LOSS_ONLY makes no sense for the MTTKRP");
+    gcp_sample_params sp{};
+    sp.kind = t->dense ? GCP_SAMPLE_UNIFORM : GCP_SAMPLE_STRATIFIED;
+    sp.p = n;
+    sp.q = 0;
+    gcp_samples smp{coords, y, nullptr};
+    return gcp::loss_grad_with_workspace(t, &sp, &smp, A, R, (gcp_loss)gcp::kLossGivenValues, flags, scale_dev, G_out,
+                                         nullptr, tile, gcp::reserved_workspace(t), stream);
 }
