@@ -40,6 +40,7 @@ class SolverConfig:
     lower: float = float("-inf")
     seed: int = 20353
     tile: G.Tile | None = None
+    fused: bool = True                 # False: the non-fused gradient (write the sampled tensor, then MTTKRP)
 
 
 @dataclass
@@ -65,6 +66,23 @@ def gcp_adam(tensor, A0: torch.Tensor, cfg: SolverConfig) -> SolverResult:
         _, L = G.gcp_loss_grad(tensor, obj_sp, A, cfg.R, cfg.loss, loss_only=True)
         return float(L.item())
 
+    nonfused_bufs = None
+    if not cfg.fused:
+        n = cfg.p + (cfg.q if cfg.sampling != "uniform" else 0)
+        nonfused_bufs = (torch.empty(n, tensor.d, dtype=torch.int64, device=A.device),
+                         torch.empty(n, dtype=A.dtype, device=A.device))
+
+    def gradient(sp):
+        if cfg.fused:
+            G.gcp_loss_grad(tensor, sp, A, cfg.R, cfg.loss, G=Gr, accumulate=True, want_loss=False, tile=cfg.tile)
+        else:
+            # Sec. 3.1.2 without fusion: the sampled tensor (coordinates and
+            # derivative values) goes to memory, then the MTTKRP reads it and
+            # gathers the factor rows a second time
+            coords, y = nonfused_bufs
+            G.gcp_sample_y(tensor, sp, A, cfg.R, cfg.loss, coords=coords, y=y)
+            G.gcp_mttkrp(tensor, coords, y, A, cfg.R, G=Gr, accumulate=True, tile=cfg.tile)
+
     res = SolverResult(A=A)
     f_prev = objective()
     res.objective.append(f_prev)
@@ -76,8 +94,7 @@ def gcp_adam(tensor, A0: torch.Tensor, cfg: SolverConfig) -> SolverResult:
         for _ in range(cfg.iters_per_epoch):
             sp = G.SampleParams(cfg.sampling, cfg.p, cfg.q if cfg.sampling != "uniform" else 0,
                                 seed=cfg.seed, step=it)
-            G.gcp_loss_grad(tensor, sp, A, cfg.R, cfg.loss, G=Gr, accumulate=True, want_loss=False,
-                            tile=cfg.tile)
+            gradient(sp)
             t += 1
             it += 1
             G.gcp_adam_step(A, Gr, B, C, t, lr=rate, beta1=cfg.beta1, beta2=cfg.beta2, eps=cfg.eps,

@@ -21,13 +21,15 @@ def _case(gpu):
     return dims, R, t, to, A0
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("lr", [5e-3, 3.0])
-def test_epoch_driver_matches_oracle(gpu, lr):
+def test_epoch_driver_matches_oracle(gpu, lr, fused):
     """lr 5e-3 lowers the objective epoch after epoch; lr 3.0 makes epochs fail,
-    which restores the model and decays the rate until three failures."""
+    which restores the model and decays the rate until three failures.  The
+    gradient fused, or non-fused (sampled tensor written, then its MTTKRP)."""
     dims, R, t, to, A0 = _case(gpu)
     cfg = SolverConfig(R=R, loss="poisson", p=300, q=300, obj_p=2000, obj_q=2000, iters_per_epoch=10,
-                       max_epochs=6, lr=lr, decay=0.1, max_fails=3, lower=0.0, seed=77)
+                       max_epochs=6, lr=lr, decay=0.1, max_fails=3, lower=0.0, seed=77, fused=fused)
     res = gcp_adam(t, A0.to(gpu), cfg)
     A, objs, rates, fails = oracle.gcp_adam_epochs(
         to, R, A0.numpy(), "poisson", 300, 300, 2000, 2000, 10, 6, lr, 0.1, 3, 77, OBJECTIVE_CLIENT,
