@@ -456,6 +456,72 @@ def hbm_resident(dev, nnz: int, steps: int, warmup: int):
             "frac": alg / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def _counter_rows(d: str):
+    """Rows of the rocprofv3 --pmc CSV output under directory d."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def _median_counter(rows, counter: str, kernel_sub: str) -> float:
+    vals = [float(r["Counter_Value"]) for r in rows
+            if r.get("Counter_Name") == counter and kernel_sub in r.get("Kernel_Name", "")]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {kernel_sub!r}")
+    return float(np.median(vals)), len(vals)
+
+
+def traffic_summary(dirs, tile: G.Tile) -> dict:
+    """DRAM bytes per sampled-gradient call from four rocprofv3 --pmc runs,
+    each counter scaled by what it reads for a copy kernel of known size;
+    written to profiles/loss_grad_cfg2_traffic.json."""
+    fetch, write, cfetch, cwrite = (_counter_rows(d) for d in dirs)
+    out = {"kernel_source_hash": kernel_source_hash(), "tile": tile_dict(tile)}
+    cf, _ = _median_counter(cfetch, "FETCH_SIZE", "k_ceil_copy")
+    cw, _ = _median_counter(cwrite, "WRITE_SIZE", "k_ceil_copy")
+    copy_bytes = 1 << 30
+    ff, fw = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    out["copy_calibration"] = {"kernel": "k_ceil_copy", "bytes": copy_bytes, "fetch_size_kib": cf,
+                               "write_size_kib": cw, "fetch_factor": ff, "write_factor": fw}
+    per = {}
+    total_r = total_w = 0.0
+    for name in ("k_loss_grad", "k_bucket_accum", "k_adam"):
+        try:
+            kf, nd = _median_counter(fetch, "FETCH_SIZE", name)
+            kw, _ = _median_counter(write, "WRITE_SIZE", name)
+        except SystemExit:
+            continue
+        per[name] = {"fetch_size_kib": kf, "write_size_kib": kw, "read_bytes": kf * 1024 * ff,
+                     "write_bytes": kw * 1024 * fw, "dispatches": nd}
+        if name != "k_adam":
+            total_r += kf * 1024 * ff
+            total_w += kw * 1024 * fw
+    out["per_kernel"] = per
+    out["read_bytes_per_launch"] = int(total_r)
+    out["write_bytes_per_launch"] = int(total_w)
+    out["bytes_per_launch"] = int(total_r + total_w)
+    out["what"] = ("DRAM bytes per gcp_loss_grad call of the benchmark step (k_loss_grad + k_bucket_accum), median "
+                   "over dispatches, calibrated against a 1 GiB copy kernel")
+    ts = ",".join(f"{k}={v}" for k, v in tile_dict(tile).items())
+    out["commands"] = [
+        f"rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_loss_grad|k_bucket_accum|k_adam' --output-format csv "
+        f"-d {dirs[0]} -o cfg2 -- python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras --tile {ts}",
+        f"rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'k_loss_grad|k_bucket_accum|k_adam' --output-format csv "
+        f"-d {dirs[1]} -o cfg2 -- python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-extras --tile {ts}",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {dirs[2]} -o copy -- python3 bench.py --copy-calibration",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {dirs[3]} -o copy -- python3 bench.py --copy-calibration",
+        "python3 bench.py --traffic-summary " + " ".join(dirs) + f" --tile {ts}"]
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 ENGINE_CLOCK_HZ = 2.4e9      # MI355X peak engine clock
 CUS = 256
 
@@ -575,6 +641,9 @@ def main():
     ap.add_argument("--hbm-resident", action="store_true",
                     help="only run the HBM-resident-factor experiment (Amazon-shaped tensor) and print its JSON")
     ap.add_argument("--hbm-nnz", type=int, default=500_000_000)
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/loss_grad_cfg2_traffic.json from four rocprofv3 --pmc runs (FETCH_SIZE and "
+                         "WRITE_SIZE of the benchmark at --tile, then of --copy-calibration) and print it")
     ap.add_argument("--ceilings", action="store_true",
                     help="only measure the hardware ceilings of the sampled gradient's access patterns and the "
                          "lower bound they put on the benchmark call; print their JSON")
@@ -597,13 +666,19 @@ def main():
         print(json.dumps(out))
         return
     if args.copy_calibration:
+        import ctypes as C
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         y = torch.empty_like(x)
         for _ in range(5):
-            y.copy_(x)
+            G._check(G.lib().gcp_ceiling_copy(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.numel() * 4,
+                                              G._stream()), "gcp_ceiling_copy")
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read_per_launch": x.numel() * 4,
+        print(json.dumps({"copy_kernel": "k_ceil_copy", "copy_bytes_read_per_launch": x.numel() * 4,
                           "copy_bytes_written_per_launch": x.numel() * 4}))
+        return
+    if args.traffic_summary:
+        print(json.dumps(traffic_summary(args.traffic_summary, parse_tile(args.tile) if args.tile else G.Tile()),
+                         indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path; "

@@ -24,8 +24,6 @@ struct LGParams {
     int semi;             // semi-stratified: samples s < p get f'(x,m) - f'(0,m)
     const T* scale;       // nullable device scalar
     double* loss_out;     // nullable
-    T* y_out;             // SRC = 2: each sample's y (the sampled tensor's values) ...
-    int64_t* c_out;       // ... and coordinates [n x d], written instead of scattering
     int64_t rowoff[kMaxModes];
     uint32_t lds_mask;    // modes accumulated in LDS
     int64_t lds_off[kMaxModes];
@@ -49,6 +47,12 @@ struct LGParams {
     int64_t bwg_base[kMaxModes + 1];
     int bsplits[kMaxModes];
     int bsegs[kMaxModes];
+    // non-fused sampling step (SRC = 2): each sample's y, the sampled
+    // tensor's values, and its coordinates [n x d], written instead of
+    // scattering (last, so that the fields above keep their kernel-argument
+    // offsets)
+    T* y_out;
+    int64_t* c_out;
 };
 
 __device__ __forceinline__ void wave_sync()
