@@ -347,7 +347,8 @@ typedef struct gcp_fed_desc {
                                  to every gcp_loss_grad call (-1 = that call's
                                  automatic choice, which row-buckets only when
                                  the client tensor has a gcp_tensor_reserve
-                                 workspace; 0 = hardware atomics).
+                                 workspace, and with lanes and vec left 0 also
+                                 its own lane shape; 0 = hardware atomics).
                                  batched: bitmask of modes scattered by the row-
                                  bucketed (sort-by-row) scheme inside the launch:
                                  each client's workgroups sort their samples by
@@ -399,7 +400,8 @@ typedef struct gcp_fed_info {
     int32_t bucket_modes;         /* batched: row-bucketed modes; per-client: the
                                      request passed to every gcp_loss_grad       */
     int32_t workgroups_per_client;/* batched                                      */
-    int32_t block, lanes, vec;    /* launch shape of the gradient part           */
+    int32_t block, lanes, vec;    /* launch shape of the gradient part (0: each
+                                     call's own choice)                         */
     int32_t bucket_block_samples; /* row-bucketed form: samples per sorted block */
     int64_t launches_per_round;   /* kernel launches one round issues (per-client
                                      rounds that may row-bucket: at most)        */

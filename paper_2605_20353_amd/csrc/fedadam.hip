@@ -730,8 +730,11 @@ static gcp_status fed_round_plain(gcp_fed_s* f, int64_t round, hipStream_t strea
     k_fed_copy<T><<<dim3(cb, (unsigned)D.nclients), 256, 0, stream>>>(a);
     GCP_HIP(hipGetLastError());
     gcp_tile tile{};
-    tile.lanes = f->lanes;
-    tile.vec = f->vec;
+    // with the automatic scatter, each call also picks its own lane shape
+    // (four columns per lane when it row-buckets), unless one was asked for
+    const bool auto_shape = D.bucket_modes != 0 && D.lanes <= 0 && D.vec <= 0;
+    tile.lanes = auto_shape ? 0 : f->lanes;
+    tile.vec = auto_shape ? 0 : f->vec;
     tile.lds_modes = -1;       // the per-launch automatic choice
     tile.bucket_modes = D.bucket_modes;
     for (int j = 0; j < D.tau; ++j) {
@@ -953,6 +956,16 @@ gcp_status gcp_fedadam_info(gcp_fed f, gcp_fed_info* out)
         i.form = GCP_FED_PER_CLIENT;
         i.lds_modes = -1;
         i.bucket_modes = D.bucket_modes;
+        if (D.bucket_modes != 0 && D.lanes <= 0 && D.vec <= 0) {
+            // the lane shape is each call's own choice
+            *out = i;
+            out->workgroups_per_client = 0;
+            out->block = 0;
+            out->lanes = 0;
+            out->vec = 0;
+            out->launches_per_round = 3 + K * D.tau * 3;
+            return GCP_OK;
+        }
         // round number, copy, server; per client and step the gradient (one
         // launch, two when it row-buckets) and Adam
         i.launches_per_round = 3 + K * D.tau * (D.bucket_modes != 0 ? 3 : 2);
