@@ -47,8 +47,9 @@ P = Q = 1 << 20
 DATA_SEED = 2607
 SAMPLE_SEED = 20353
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loss_grad_cfg2_traffic.json")
-KERNEL_SOURCES = ["paper_2605_20353_amd/csrc/loss_grad.hip", "paper_2605_20353_amd/csrc/lg_core.hpp",
-                  "paper_2605_20353_amd/csrc/sampling.hpp", "paper_2605_20353_amd/csrc/gcp_internal.hpp"]
+KERNEL_SOURCES = ["paper_2605_20353_amd/csrc/loss_grad.hip", "paper_2605_20353_amd/csrc/lg_kernels.hpp",
+                  "paper_2605_20353_amd/csrc/lg_core.hpp", "paper_2605_20353_amd/csrc/sampling.hpp",
+                  "paper_2605_20353_amd/csrc/gcp_internal.hpp"]
 
 
 def log(msg: str) -> None:
@@ -734,13 +735,18 @@ def main():
         f"DRAM {dram_gbs or float('nan'):.0f} GB/s; algorithmic model {alg_gbs:.0f} GB/s")
     roof["tile"] = tile_dict(tile)
     roof["tile_source"] = tile_source
+    # the bit-reproducible form of the same call (GCP_DETERMINISTIC)
+    Gd = torch.zeros_like(A)
+    det_ms = _median_ms(lambda: G.gcp_loss_grad(t, sp0, A, RANK, "poisson", G=Gd, want_loss=False,
+                                                deterministic=True), 10, 2)
+    log(f"deterministic call {det_ms:.3f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(data, A0, args.cpu_steps, args.cpu_par_steps)
         log(f"cpu baseline {cpu['value']:.4g} samples/s")
     del data, t
     torch.cuda.empty_cache()
-    extras = {}
+    extras = {"deterministic_call_ms": det_ms}
     if not args.no_extras:
         extras["fedadam"] = run_fedadam(dev, args.fed_rounds)
         torch.cuda.empty_cache()

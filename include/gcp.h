@@ -147,6 +147,17 @@ typedef struct gcp_tile {
 #define GCP_SCALE_BY_DEV 4u     /* multiply every y by *scale_dev (device
                                    scalar of the tensor dtype); the objective
                                    is not scaled                               */
+#define GCP_DETERMINISTIC 8u    /* bit-identical gradient and objective on
+                                   every run with the same samples, model,
+                                   tile and device: the sampled tensor is
+                                   written, its (row, sample) pairs sorted by
+                                   row (a stable radix sort), and each gradient
+                                   row summed by one wavefront in sample order;
+                                   the objective's per-wavefront partial sums
+                                   are added in a fixed order.  Drawn samples
+                                   only (smp must be NULL); needs the workspace
+                                   of gcp_tensor_reserve; slower than the
+                                   default scatter                             */
 /* gcp_adam_step flags */
 #define GCP_ADAM_ZERO_GRAD 1u   /* write G = 0 after reading it                */
 
@@ -192,9 +203,12 @@ gcp_status gcp_tensor_destroy(gcp_tensor t);
 int64_t gcp_tensor_device_bytes(gcp_tensor t);
 
 /* Reserves the handle's workspace for the row-bucketed gradient scatter
- * (sort-by-row MTTKRP, Sec. 3.1.2) for calls with up to max_samples = p + q
- * samples at rank R: about 16 (max_samples + 8192) d bytes of sample entries
- * plus per-(row block, workgroup) counts.  Without a reservation every large
+ * (sort-by-row MTTKRP, Sec. 3.1.2) and for GCP_DETERMINISTIC calls, for calls
+ * with up to max_samples = p + q samples at rank R: about 16 (max_samples +
+ * 8192) d bytes of sample entries plus per-(row block, workgroup) counts, or
+ * what the deterministic form needs (coordinates and derivative values of
+ * the sampled tensor, (row, sample) pairs and their sort), whichever is
+ * larger.  Without a reservation every large
  * mode uses hardware atomics.  Calls that use the workspace of one handle
  * must be ordered (one stream, or synchronised); concurrent calls race.
  * Replaces any earlier reservation (synchronises the device first). */

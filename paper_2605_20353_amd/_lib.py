@@ -39,6 +39,7 @@ SAMPLING = {"stratified": 0, "uniform": 1, "semi_stratified": 2}
 GCP_LOSS_ONLY = 1
 GCP_ACCUMULATE = 2
 GCP_SCALE_BY_DEV = 4
+GCP_DETERMINISTIC = 8
 GCP_ADAM_ZERO_GRAD = 1
 
 
@@ -321,9 +322,11 @@ def gcp_loss_grad(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, lo
                   G: torch.Tensor | None = None, loss_out: torch.Tensor | None = None,
                   samples=None, loss_only: bool = False, accumulate: bool = False,
                   scale: torch.Tensor | None = None, tile: Tile | None = None, want_loss: bool = True,
-                  stream=None, noalloc: bool = False):
+                  stream=None, noalloc: bool = False, deterministic: bool = False):
     """Fused sampled objective and gradient.  Returns (G, loss_out) where
-    loss_out is a 1-element float64 device tensor (or None).  noalloc=True
+    loss_out is a 1-element float64 device tensor (or None).
+    deterministic=True sets GCP_DETERMINISTIC (bit-identical runs; needs
+    the tensor's reserved workspace).  noalloc=True
     calls gcp_loss_grad_noalloc (the library's fixed scratch region instead
     of the handle's reserved workspace); G and loss_out should then be passed
     in, or they are allocated here by torch before the call."""
@@ -349,6 +352,8 @@ def gcp_loss_grad(t: SparseTensor, sp: SampleParams, A: torch.Tensor, R: int, lo
         if scale.dtype != A.dtype:
             raise TypeError("scale dtype must match the model dtype")
         flags |= GCP_SCALE_BY_DEV
+    if deterministic:
+        flags |= GCP_DETERMINISTIC
     smp_p = None
     keep = None
     if samples is not None:

@@ -360,7 +360,19 @@ struct LGWorkspace {
 struct LGOutputs {
     void* y_out = nullptr;          // [n] tensor dtype
     int64_t* coords_out = nullptr;  // [n x d]
+    double* loss_parts = nullptr;   // per-wave objective partials (deterministic objective)
+    int64_t loss_parts_cap = 0;     // slots available
+    int64_t* parts_used = nullptr;  // receives the number of slots the launch fills
 };
+
+// Bytes of workspace the deterministic sampled gradient needs for up to
+// max_samples samples (deterministic.hip); -1 on failure.
+int64_t det_workspace_bytes(const gcp_tensor_s* t, int64_t max_samples);
+
+// gcp_loss_grad with GCP_DETERMINISTIC (deterministic.hip).
+gcp_status loss_grad_deterministic(gcp_tensor_s* t, const gcp_sample_params* sp, const gcp_samples* smp,
+                                   const void* A, int R, gcp_loss loss, unsigned flags, const void* scale_dev,
+                                   void* G_out, double* loss_out, const gcp_tile* tile, hipStream_t stream);
 
 // gcp_loss_grad with an explicit bucketed-scatter workspace (the argument
 // checks and launches of loss_grad.hip).

@@ -53,6 +53,9 @@ struct LGParams {
     // offsets)
     T* y_out;
     int64_t* c_out;
+    // deterministic objective: each wave's partial sum goes to its own slot
+    // (workgroup * waves + wave) instead of an atomic add into loss_out
+    double* loss_parts;
 };
 
 __device__ __forceinline__ void wave_sync()

@@ -58,7 +58,11 @@ __global__ void __launch_bounds__(1024) k_loss_grad(const LGParams<T> P)
 
     if (P.loss_out) {
         for (int off = 32; off >= 1; off >>= 1) lacc += xor_shfl(lacc, off);
-        if (lane == 0 && lacc != 0.0) atomicAdd(P.loss_out, lacc);
+        if (P.loss_parts) {
+            if (lane == 0) P.loss_parts[(int64_t)blockIdx.x * nwaves + wave] = lacc;
+        } else if (lane == 0 && lacc != 0.0) {
+            atomicAdd(P.loss_out, lacc);
+        }
     }
     if (P.lds_mask) {
         __syncthreads();

@@ -296,6 +296,14 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
         P.y_out = (T*)xo->y_out;
         P.c_out = xo->coords_out;
     }
+    if (xo && xo->loss_parts && loss_out) {
+        if (bucket_mask) return set_error(GCP_ERR_ARG, "per-wave objective partials need an unbucketed launch");
+        if (grid * nwaves > xo->loss_parts_cap)
+            return set_error(GCP_ERR_ARG, "%lld objective partials exceed the %lld slots", (long long)(grid * nwaves),
+                             (long long)xo->loss_parts_cap);
+        P.loss_parts = xo->loss_parts;
+        if (xo->parts_used) *xo->parts_used = grid * nwaves;
+    }
     for (int k = 0; k < kMaxModes; ++k) P.rowoff[k] = k < d ? t->rowoff[k] : t->rowoff[d];
     P.lds_mask = lds_mask;
     P.lds_elems = lds_elems;
@@ -405,6 +413,8 @@ extern "C" gcp_status gcp_loss_grad(gcp_tensor t, const gcp_sample_params* sp, c
 {
     gcp::clear_error();
     if (!t) return gcp::set_error(GCP_ERR_ARG, "tensor is NULL");
+    if (flags & GCP_DETERMINISTIC)
+        return gcp::loss_grad_deterministic(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile, stream);
     return gcp::loss_grad_with_workspace(t, sp, smp, A, R, loss, flags, scale_dev, G_out, loss_out, tile,
                                          gcp::reserved_workspace(t), stream);
 }

@@ -59,6 +59,8 @@ extern "C" gcp_status gcp_loss_grad_noalloc(gcp_tensor t, const gcp_sample_param
 {
     gcp::clear_error();
     if (!t) return gcp::set_error(GCP_ERR_ARG, "tensor is NULL");
+    if (flags & GCP_DETERMINISTIC)
+        return gcp::set_error(GCP_ERR_UNSUPPORTED, "GCP_DETERMINISTIC needs the workspace of gcp_tensor_reserve");
     gcp::LGWorkspace ws;
     gcp_status st = gcp::scratch_on(t->device, &ws.base);
     if (st != GCP_OK) return st;

@@ -316,7 +316,9 @@ gcp_status gcp_tensor_reserve(gcp_tensor t, int64_t max_samples, int R, hipStrea
     const int64_t nblocks = ceil_div(max_samples, 512);
     const int64_t entries = (max_samples + 8192) * t->d;
     const int64_t hist = nb * nblocks;
-    const int64_t bytes = entries * 16 + hist * 8;
+    // the same region serves GCP_DETERMINISTIC calls
+    const int64_t det = max_samples < (int64_t(1) << 32) ? det_workspace_bytes(t, max_samples) : 0;
+    const int64_t bytes = std::max<int64_t>(entries * 16 + hist * 8, det);
     hipError_t e = hipMalloc(&t->ws, (size_t)bytes);
     if (e != hipSuccess) {
         t->ws = nullptr;

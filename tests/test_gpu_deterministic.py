@@ -1,0 +1,112 @@
+"""GCP_DETERMINISTIC: the sampled gradient and objective are bit-identical on
+repeated runs (the sampled tensor written, its (row, sample) pairs sorted by
+row with a stable sort, each gradient row summed by one wavefront in sample
+order, the objective's per-wavefront partials added in slot order), and they
+are the oracle's gradient and objective within the rounding bound, for every
+loss, 3- and 4-way tensors, both dtypes, with scale and accumulation."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2605_20353_amd import _lib as G
+from paper_2605_20353_amd import synth
+from parity_util import assert_grad_close, frob_rel_errs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(gpu, dtype, dims, nnz, binary, seed):
+    data = synth.count_tensor(dims, 3, nnz, seed=seed, binary=binary)
+    t = G.SparseTensor(dims, data.coords.to(gpu), data.vals.to(dtype).to(gpu))
+    to = oracle.SparseTensor(dims, data.coords.numpy(), data.vals.to(dtype).double().numpy())
+    return t, to
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("loss", ["poisson", "gaussian", "bernoulli_logit"])
+@pytest.mark.parametrize("shape", ["3way", "4way"])
+def test_deterministic_runs_are_identical_and_match_oracle(gpu, dtype, loss, shape):
+    dims, R, nnz = ([900, 700, 500], 32, 20000) if shape == "3way" else ([60, 50, 40, 30], 16, 8000)
+    t, to = _case(gpu, dtype, dims, nnz, loss == "bernoulli_logit", seed=2661)
+    if loss == "poisson":
+        A = (0.2 + 0.8 * synth.init_model(dims, R, 7, dtype=torch.float64)).to(dtype).to(gpu)
+    else:
+        A = (0.5 * synth.init_model(dims, R, 7, dist="normal", dtype=torch.float64)).to(dtype).to(gpu)
+    sp = G.SampleParams("stratified", 40000 + 37, 30000 + 11, seed=20353, step=4)
+    t.reserve(sp.n, R)
+    say(f"deterministic {shape} {loss} {dtype}")
+    runs = []
+    for _ in range(3):
+        Gd, Ld = G.gcp_loss_grad(t, sp, A, R, loss, deterministic=True)
+        runs.append((Gd.clone(), Ld.clone()))
+    t.status()
+    for Gd, Ld in runs[1:]:
+        assert torch.equal(Gd, runs[0][0]), "gradient differs between runs"
+        assert torch.equal(Ld, runs[0][1]), "objective differs between runs"
+    sc, sx, sw = oracle.sample_stratified(to, sp.p, sp.q, sp.seed, sp.step)
+    A64 = A.double().cpu().numpy().reshape(-1)
+    Go, Fo = oracle.loss_grad(dims, R, A64, sc, sx, sw, loss)
+    assert_grad_close(runs[0][0].cpu().numpy(), Go, dims, R, A64, sc, sx, sw, loss, dtype,
+                      what=f"deterministic {shape} {loss}")
+    assert abs(runs[0][1].item() - Fo) <= TOL[dtype] * abs(Fo)
+    # the default scatter gives the same gradient within the tolerance
+    Gf, _ = G.gcp_loss_grad(t, sp, A, R, loss)
+    assert max(frob_rel_errs(Gf.cpu().numpy(), runs[0][0].cpu().numpy(), dims, R)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_deterministic_scale_accumulate_and_empty(gpu, dtype):
+    dims, R = [300, 200, 100], 8
+    t, to = _case(gpu, dtype, dims, 5000, False, seed=2662)
+    A = (0.2 + 0.8 * synth.init_model(dims, R, 9, dtype=torch.float64)).to(dtype).to(gpu)
+    sp = G.SampleParams("stratified", 3000, 2001, seed=5, step=1)
+    t.reserve(sp.n, R)
+    scale = torch.tensor([-2.0], dtype=dtype, device=gpu)
+    G1, L1 = G.gcp_loss_grad(t, sp, A, R, "poisson", scale=scale, deterministic=True)
+    G2, L2 = G.gcp_loss_grad(t, sp, A, R, "poisson", G=G1.clone(), loss_out=L1.clone(), accumulate=True,
+                             deterministic=True)
+    t.status()
+    sc, sx, sw = oracle.sample_stratified(to, sp.p, sp.q, sp.seed, sp.step)
+    A64 = A.double().cpu().numpy().reshape(-1)
+    Go, Fo = oracle.loss_grad(dims, R, A64, sc, sx, sw, "poisson")
+    assert_grad_close(G1.cpu().numpy(), -2.0 * Go, dims, R, A64, sc, sx, sw, "poisson", dtype, scale=2.0,
+                      what="scaled")
+    assert_grad_close(G2.cpu().numpy(), -1.0 * Go, dims, R, A64, sc, sx, sw, "poisson", dtype, scale=4.0,
+                      what="accumulated")
+    assert abs(L1.item() - Fo) <= TOL[dtype] * abs(Fo)           # the objective is not scaled
+    assert abs(L2.item() - 2 * Fo) <= TOL[dtype] * abs(2 * Fo)
+    G0, L0 = G.gcp_loss_grad(t, G.SampleParams("stratified", 0, 0), A, R, "poisson", G=torch.full_like(A, 3.0),
+                             deterministic=True)
+    assert torch.count_nonzero(G0).item() == 0 and L0.item() == 0.0
+
+
+def test_deterministic_errors(gpu):
+    dims, R = [30, 20, 10], 4
+    t, _ = _case(gpu, torch.float32, dims, 300, False, seed=2663)
+    A = torch.rand(sum(dims) * R, device=gpu)
+    sp = G.SampleParams("stratified", 100, 100, seed=1)
+    with pytest.raises(G.GCPError) as e:                       # no reserved workspace
+        G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
+    assert e.value.code == G.GCP_ERR_ARG
+    t.reserve(sp.n, R)
+    smp = G.gcp_sample(t, sp)
+    with pytest.raises(G.GCPError) as e:                       # drawn samples only
+        G.gcp_loss_grad(t, sp, A, R, "poisson", samples=smp, deterministic=True)
+    assert e.value.code == G.GCP_ERR_UNSUPPORTED
+    with pytest.raises(G.GCPError) as e:                       # more samples than reserved
+        G.gcp_loss_grad(t, G.SampleParams("stratified", 1000, 1000), A, R, "poisson", deterministic=True)
+    assert e.value.code == G.GCP_ERR_ARG
+    Gn = torch.empty_like(A)
+    with pytest.raises(G.GCPError) as e:                       # not with the fixed scratch region
+        G.gcp_loss_grad_noalloc(t, sp, A, R, "poisson", Gn, deterministic=True)
+    assert e.value.code == G.GCP_ERR_UNSUPPORTED

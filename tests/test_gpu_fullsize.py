@@ -46,7 +46,10 @@ def test_config2_full_size_samples_and_gradient(gpu):
     c, x, w = G.gcp_sample(t, sp)
     Ga, La = G.gcp_loss_grad(t, sp, A, R, "poisson", tile=G.Tile(bucket_modes=0, lds_modes=0))
     Gb, Lb = G.gcp_loss_grad(t, sp, A, R, "poisson")                     # automatic: row-bucketed
+    Gd, Ld = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
+    Gd2, Ld2 = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
     t.status()
+    assert torch.equal(Gd, Gd2) and torch.equal(Ld, Ld2), "deterministic runs differ"
     say(f"config 2: GPU side done in {time.time() - t0:.1f} s; building the oracle's sorted index")
     coords = data.coords.cpu().numpy()
     vals = data.vals.to(torch.float32).double().cpu().numpy()
@@ -61,7 +64,7 @@ def test_config2_full_size_samples_and_gradient(gpu):
     say(f"config 2: oracle gradient at {time.time() - t0:.1f} s")
     Go = Go.reshape(-1, R)
     A64 = A.double().cpu().numpy().reshape(-1)
-    for name, (Gx, Lx) in (("atomic", (Ga, La)), ("bucketed", (Gb, Lb))):
+    for name, (Gx, Lx) in (("atomic", (Ga, La)), ("bucketed", (Gb, Lb)), ("deterministic", (Gd, Ld))):
         # every element within the rounding bound of float32 arithmetic in
         # any summation order, and per mode within 1e-5 relative
         frob, worst = assert_grad_close(Gx.cpu().numpy(), Go, dims, R, A64, oc, ox, ow, "poisson", torch.float32,
