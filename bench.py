@@ -447,12 +447,29 @@ def hbm_resident(dev, nnz: int, steps: int, warmup: int):
     t.status()
     kms = [a.elapsed_time(b) for a, b in ev]
     kmed = float(np.median(kms))
+    # the same samples through the row-sorted form (GCP_DETERMINISTIC): the
+    # sampled tensor written, its (row, sample) pairs sorted by row, each
+    # touched gradient row summed by one wavefront and written with a plain
+    # load-add-store -- against one float-atomic request per (sample, mode)
+    t.reserve(P + Q, R)
+    sms = []
+    for k in range(5):
+        sp = G.SampleParams("stratified", P, Q, seed=SAMPLE_SEED, step=k)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        G.gcp_loss_grad(t, sp, A, R, "poisson", G=Gr, accumulate=True, want_loss=False, deterministic=True)
+        b.record()
+        torch.cuda.synchronize()
+        if k:
+            sms.append(a.elapsed_time(b))
+    t.status()
     alg = algorithmic_bytes(3, R, P, Q)
     return {"workload": f"Amazon-shaped count tensor {dims[0]}x{dims[1]}x{dims[2]}, {nnz} nonzeros, rank {R} "
                         f"FP32, {P}+{Q} stratified samples per step (mixed-radix cell keys)",
             "factor_bytes": A.numel() * 4, "tensor_handle_bytes": t.device_bytes(), "generation_s": gen_s,
             "steps": steps, "samples_per_s": steps * (P + Q) / wall, "ms_per_step": 1e3 * wall / steps,
-            "loss_grad_ms_median": kmed, "algorithmic_bytes_per_launch": alg,
+            "loss_grad_ms_median": kmed, "sorted_rows_plain_stores_ms_median": float(np.median(sms)),
+            "algorithmic_bytes_per_launch": alg,
             "algorithmic_gbs": alg / (kmed * 1e-3) / 1e9,
             "frac": alg / (kmed * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
@@ -492,13 +509,17 @@ def traffic_summary(dirs, tile: G.Tile) -> dict:
                                "write_size_kib": cw, "fetch_factor": ff, "write_factor": fw}
     per = {}
     total_r = total_w = 0.0
-    for name in ("k_loss_grad", "k_bucket_accum", "k_adam"):
+    # the exact instantiations of the benchmark's call (SRC = 0: samples drawn
+    # in the kernel; the tile's lane shape)
+    shape = f"3, {tile.lanes}, {tile.vec}"
+    for name, match in (("k_loss_grad", f"k_loss_grad<float, {shape}, 0>"),
+                        ("k_bucket_accum", f"k_bucket_accum<float, {shape}>"), ("k_adam", "k_adam<float>")):
         try:
-            kf, nd = _median_counter(fetch, "FETCH_SIZE", name)
-            kw, _ = _median_counter(write, "WRITE_SIZE", name)
+            kf, nd = _median_counter(fetch, "FETCH_SIZE", match)
+            kw, _ = _median_counter(write, "WRITE_SIZE", match)
         except SystemExit:
             continue
-        per[name] = {"fetch_size_kib": kf, "write_size_kib": kw, "read_bytes": kf * 1024 * ff,
+        per[name] = {"kernel": match, "fetch_size_kib": kf, "write_size_kib": kw, "read_bytes": kf * 1024 * ff,
                      "write_bytes": kw * 1024 * fw, "dispatches": nd}
         if name != "k_adam":
             total_r += kf * 1024 * ff
@@ -536,9 +557,10 @@ def ceilings(dev, reps: int = 10):
         dependent row gathers, at the dependent-gather rate, overlapped with
         writing its 3 x 16-byte sort entries at the copy rate;
       owner pass: per entry (3 per sample) two row gathers from a streamed
-        entry, at the streamed-gather rate, and 16 lanes' 64-bit LDS
-        compare-and-swap adds at the measured LDS rate, overlapped with
-        reading the entries back at the copy rate;
+        entry, at the streamed-gather rate, and R float adds into the LDS row
+        block by compare-and-swap pairs, at the rate measured for the owner's
+        pattern (8 lanes x 4 columns into rows drawn at random), overlapped
+        with reading the entries back at the copy rate;
       the two kernels run one after the other.
     The bound is the sum over the two kernels of the slowest part of each."""
     import ctypes as C
@@ -585,6 +607,11 @@ def ceilings(dev, reps: int = 10):
     out["lds_cas64"] = {"lane_ops_per_s": lane_ops / (ms * 1e-3),
                         "wave_instr_per_clk_per_cu": lane_ops / 64 / (ms * 1e-3) / (CUS * ENGINE_CLOCK_HZ),
                         "ms": ms}
+    iters_r = 2048
+    for form, name in ((0, "cas64_pairs"), (1, "native_ds_add_f32")):
+        ms = timed(lambda: L.gcp_ceiling_lds_row_adds(form, iters_r, grid, C.c_void_p(sink.data_ptr()), st))
+        out.setdefault("lds_row_adds", {})[name] = {"float_adds_per_s": grid * 1024 * iters_r * 4 / (ms * 1e-3),
+                                                    "ms": ms}
     Gr = torch.zeros(sum(DIMS) * RANK, dtype=torch.float32, device=dev)
     nup = 1 << 22
     ms = timed(lambda: L.gcp_ceiling_global_atomics(C.c_void_p(Gr.data_ptr()), sum(DIMS), nup, 512, st))
@@ -602,7 +629,7 @@ def ceilings(dev, reps: int = 10):
     t_draw = n / out["dependent_record_3_row_gathers"]["samples_per_s"]
     t_write = n * d * ent_bytes / copy_bps
     t_owner_gather = n * d * 2 / out["streamed_record_3_row_gathers"]["rows_per_s"]
-    t_owner_cas = n * d * (RANK // 2) / out["lds_cas64"]["lane_ops_per_s"]
+    t_owner_cas = n * d * RANK / out["lds_row_adds"]["cas64_pairs"]["float_adds_per_s"]
     t_read = n * d * ent_bytes / copy_bps
     parts_a = {"dependent record and row gathers": t_draw, "sort-entry writes": t_write}
     parts_b = {"streamed-entry row gathers": t_owner_gather, "LDS compare-and-swap adds": t_owner_cas,
@@ -735,18 +762,20 @@ def main():
         f"DRAM {dram_gbs or float('nan'):.0f} GB/s; algorithmic model {alg_gbs:.0f} GB/s")
     roof["tile"] = tile_dict(tile)
     roof["tile_source"] = tile_source
-    # the bit-reproducible form of the same call (GCP_DETERMINISTIC)
-    Gd = torch.zeros_like(A)
-    det_ms = _median_ms(lambda: G.gcp_loss_grad(t, sp0, A, RANK, "poisson", G=Gd, want_loss=False,
-                                                deterministic=True), 10, 2)
-    log(f"deterministic call {det_ms:.3f} ms")
+    extras = {}
+    if not args.no_extras:
+        # the bit-reproducible form of the same call (GCP_DETERMINISTIC)
+        Gd = torch.zeros_like(A)
+        extras["deterministic_call_ms"] = _median_ms(
+            lambda: G.gcp_loss_grad(t, sp0, A, RANK, "poisson", G=Gd, want_loss=False, deterministic=True), 10, 2)
+        log(f"deterministic call {extras['deterministic_call_ms']:.3f} ms")
+        del Gd
     cpu = None
     if not args.no_cpu_baseline:
         cpu = run_cpu_baseline(data, A0, args.cpu_steps, args.cpu_par_steps)
         log(f"cpu baseline {cpu['value']:.4g} samples/s")
     del data, t
     torch.cuda.empty_cache()
-    extras = {"deterministic_call_ms": det_ms}
     if not args.no_extras:
         extras["fedadam"] = run_fedadam(dev, args.fed_rounds)
         torch.cuda.empty_cache()

@@ -152,7 +152,8 @@ typedef struct gcp_tile {
                                    tile and device: the sampled tensor is
                                    written, its (row, sample) pairs sorted by
                                    row (a stable radix sort), and each gradient
-                                   row summed by one wavefront in sample order;
+                                   row summed by one wavefront in an order
+                                   fixed by its sorted run;
                                    the objective's per-wavefront partial sums
                                    are added in a fixed order.  Drawn samples
                                    only (smp must be NULL); needs the workspace

@@ -91,6 +91,7 @@ def _declare(L):
         "gcp_ceiling_random_reads": ([vp, i64, i64, C.c_int, C.c_int, vp, vp], C.c_int),
         "gcp_ceiling_dependent_gathers": ([vp, i64, vp, C.POINTER(i64), i64, C.c_int, C.c_int, vp, vp], C.c_int),
         "gcp_ceiling_lds_cas": ([C.c_int, C.c_int, C.c_int, vp, vp], C.c_int),
+        "gcp_ceiling_lds_row_adds": ([C.c_int, C.c_int, C.c_int, vp, vp], C.c_int),
         "gcp_ceiling_global_atomics": ([vp, i64, i64, C.c_int, vp], C.c_int),
         "gcp_ceiling_copy": ([vp, vp, i64, vp], C.c_int),
         "gcp_adam_step": ([vp, vp, vp, vp, i64, C.c_int, i64, d_, d_, d_, d_, d_, u, vp], C.c_int),

@@ -13,6 +13,10 @@
 //   LDS 64-bit CAS adds    compare-and-swap adds of float pairs into LDS at
 //                          distinct words (the accumulation of the LDS-private
 //                          and row-block scatters);
+//   LDS row adds           float adds into a 256-row block of 32 floats, eight
+//                          lanes of four columns per row drawn at random (the
+//                          owner pass's pattern), by compare-and-swap pairs or
+//                          by the native LDS float atomic;
 //   global float atomics   one 128-byte row of float atomic adds per request
 //                          at random rows of a small array (the atomic scatter);
 //   stream copy            a device-to-device float4 copy (attainable HBM
@@ -124,6 +128,57 @@ __global__ void __launch_bounds__(1024) k_ceil_lds_cas(int iters, float* __restr
     if (threadIdx.x == 0 && w[0] == 7ull) sink[blockIdx.x] = 1.f;
 }
 
+// Eight lanes per row: every iteration each group of 8 lanes draws a row of
+// the 256 x 32 float block (32 KB of LDS) and each lane adds 4 floats to its
+// 4 columns.  FORM 0: two 64-bit compare-and-swap float-pair loops (the
+// owner pass's form); FORM 1: four native LDS float atomic adds.
+__device__ __forceinline__ uint32_t hmix32(uint32_t x)
+{
+    // 32-bit integer finaliser (xorshift-multiply), cheap next to the adds
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+template <int FORM>
+__global__ void __launch_bounds__(1024) k_ceil_lds_rows(int iters, float* __restrict__ sink)
+{
+    __shared__ __attribute__((aligned(16))) float blk[256 * 32];
+    for (int e = threadIdx.x; e < 256 * 32; e += blockDim.x) blk[e] = 0.f;
+    __syncthreads();
+    const uint32_t grp = threadIdx.x >> 3;
+    const int c4 = (threadIdx.x & 7) * 4;
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t row = hmix32(blockIdx.x * 0x9e3779b9u + grp * 0x85ebca6bu + (uint32_t)it * 0xc2b2ae35u) & 255u;
+        float* p = blk + row * 32 + c4;
+        if constexpr (FORM == 0) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                unsigned long long* w = reinterpret_cast<unsigned long long*>(p + 2 * h);
+                unsigned long long old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                for (;;) {
+                    const float lo = __uint_as_float((unsigned)old) + 1.0f;
+                    const float hi = __uint_as_float((unsigned)(old >> 32)) + 2.0f;
+                    const unsigned long long nv = (unsigned long long)__float_as_uint(lo) |
+                                                  ((unsigned long long)__float_as_uint(hi) << 32);
+                    if (__hip_atomic_compare_exchange_strong(w, &old, nv, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                __hip_atomic_fetch_add(p + v, 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && blk[0] == -1.f) sink[blockIdx.x] = 1.f;
+}
+
 // Groups of 32 lanes add one float each to a random row of 32 floats.
 __global__ void __launch_bounds__(1024) k_ceil_atomics(float* __restrict__ G, uint64_t rows, int64_t nupdates,
                                                      uint64_t seed)
@@ -205,6 +260,19 @@ gcp_status gcp_ceiling_lds_cas(int iters, int block, int grid, void* sink, hipSt
         return set_error(GCP_ERR_ARG, "gcp_ceiling_lds_cas arguments");
     const size_t lds = (size_t)block * 4 * 8;
     hipLaunchKernelGGL(k_ceil_lds_cas, dim3((unsigned)grid), dim3(block), lds, stream, iters, (float*)sink);
+    GCP_HIP(hipGetLastError());
+    return GCP_OK;
+}
+
+gcp_status gcp_ceiling_lds_row_adds(int form, int iters, int grid, void* sink, hipStream_t stream)
+{
+    clear_error();
+    if (!sink || iters < 1 || grid < 1 || (form != 0 && form != 1))
+        return set_error(GCP_ERR_ARG, "gcp_ceiling_lds_row_adds arguments");
+    if (form == 0)
+        hipLaunchKernelGGL(k_ceil_lds_rows<0>, dim3((unsigned)grid), dim3(1024), 0, stream, iters, (float*)sink);
+    else
+        hipLaunchKernelGGL(k_ceil_lds_rows<1>, dim3((unsigned)grid), dim3(1024), 0, stream, iters, (float*)sink);
     GCP_HIP(hipGetLastError());
     return GCP_OK;
 }

@@ -1,9 +1,10 @@
 """GCP_DETERMINISTIC: the sampled gradient and objective are bit-identical on
 repeated runs (the sampled tensor written, its (row, sample) pairs sorted by
-row with a stable sort, each gradient row summed by one wavefront in sample
-order, the objective's per-wavefront partials added in slot order), and they
-are the oracle's gradient and objective within the rounding bound, for every
-loss, 3- and 4-way tensors, both dtypes, with scale and accumulation."""
+row with a stable sort, each gradient row summed by one wavefront in an order
+fixed by the sorted run, the objective's per-wavefront partials added in slot
+order), and they are the oracle's gradient and objective within the rounding
+bound, for every loss, tensors of 1, 3, 4 and 5 modes, ranks 4 to 96, both
+dtypes, with scale and accumulation."""
 import sys
 
 import numpy as np
@@ -62,6 +63,28 @@ def test_deterministic_runs_are_identical_and_match_oracle(gpu, dtype, loss, sha
     # the default scatter gives the same gradient within the tolerance
     Gf, _ = G.gcp_loss_grad(t, sp, A, R, loss)
     assert max(frob_rel_errs(Gf.cpu().numpy(), runs[0][0].cpu().numpy(), dims, R)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("dims,R,nnz", [([300, 200, 100], 96, 4000),     # columns in two passes of 64
+                                        ([12, 10, 8, 6, 9], 5, 1500),   # general order, 8-lane groups
+                                        ([300], 4, 40)])                # one mode: the sum of y per row
+def test_deterministic_ranks_and_orders(gpu, dtype, dims, R, nnz):
+    t, to = _case(gpu, dtype, dims, nnz, False, seed=2664)
+    A = (0.2 + 0.8 * synth.init_model(dims, R, 11, dtype=torch.float64)).to(dtype).to(gpu)
+    sp = G.SampleParams("stratified", 2500 + 3, 1500 + 1, seed=20353, step=2)
+    t.reserve(sp.n, R)
+    say(f"deterministic dims={dims} R={R} {dtype}")
+    G1, L1 = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
+    G2, L2 = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
+    t.status()
+    assert torch.equal(G1, G2) and torch.equal(L1, L2), "deterministic runs differ"
+    sc, sx, sw = oracle.sample_stratified(to, sp.p, sp.q, sp.seed, sp.step)
+    A64 = A.double().cpu().numpy().reshape(-1)
+    Go, Fo = oracle.loss_grad(dims, R, A64, sc, sx, sw, "poisson")
+    assert_grad_close(G1.cpu().numpy(), Go, dims, R, A64, sc, sx, sw, "poisson", dtype,
+                      what=f"deterministic dims={dims} R={R}")
+    assert abs(L1.item() - Fo) <= TOL[dtype] * abs(Fo)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
