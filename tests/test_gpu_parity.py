@@ -304,7 +304,8 @@ BUCKET_TILES = [
 def test_bucketed_scatter_every_lane_shape(gpu, dtype, name):
     """The owner pass adds 1, 2 or 4 columns per lane (float column pairs by
     one 64-bit compare-and-swap): every lane shape, bucketed alone and with
-    the LDS-private strategy on one mode, against the oracle."""
+    the LDS-private strategy on one mode, against the oracle, with 256- and
+    1024-thread owner workgroups and one or two splits per row block."""
     t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
     pq = (20000, 9001)
     t_gpu.reserve(sum(pq), R)
@@ -313,9 +314,9 @@ def test_bucketed_scatter_every_lane_shape(gpu, dtype, name):
     ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
     every = (1 << len(dims)) - 1
     for lanes, vec in _shapes(R, dtype):
-        for lds in (0, 1):
+        for lds, bblock, splits in ((0, 256, 2), (1, 256, 2), (0, 1024, 1), (1, 1024, 2)):
             tl = dict(lanes=lanes, vec=vec, bucket_modes=every & ~lds, lds_modes=lds, bucket_block_samples=1024,
-                      bucket_splits=2, bucket_block=256)
+                      bucket_splits=splits, bucket_block=bblock)
             say(f"bucketed shape {name} {dtype} {tl}")
             Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(**tl))
             t_gpu.status()
