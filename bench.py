@@ -422,6 +422,7 @@ def hbm_resident(dev, nnz: int, steps: int, warmup: int):
     t0 = time.time()
     data = synth.count_tensor(dims, R, nnz, seed=2614, dist="gamma", device=dev)
     gen_s = time.time() - t0
+    torch.cuda.empty_cache()            # the generator's temporaries, before the handle's own allocations
     t = G.SparseTensor(dims, data.coords, data.vals.to(torch.float32))
     del data
     torch.cuda.empty_cache()
@@ -668,7 +669,7 @@ def main():
                          "'default' = the library's automatic choice")
     ap.add_argument("--hbm-resident", action="store_true",
                     help="only run the HBM-resident-factor experiment (Amazon-shaped tensor) and print its JSON")
-    ap.add_argument("--hbm-nnz", type=int, default=500_000_000)
+    ap.add_argument("--hbm-nnz", type=int, default=1_700_000_000)
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/loss_grad_cfg2_traffic.json from four rocprofv3 --pmc runs (FETCH_SIZE and "
                          "WRITE_SIZE of the benchmark at --tile, then of --copy-calibration) and print it")
