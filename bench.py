@@ -500,6 +500,8 @@ def traffic_summary(dirs, tile: G.Tile) -> dict:
     """DRAM bytes per sampled-gradient call from four rocprofv3 --pmc runs,
     each counter scaled by what it reads for a copy kernel of known size;
     written to profiles/loss_grad_cfg2_traffic.json."""
+    if not tile.lanes or not tile.vec:
+        raise SystemExit("--traffic-summary needs the profiled tile (--tile with lanes and vec)")
     fetch, write, cfetch, cwrite = (_counter_rows(d) for d in dirs)
     out = {"kernel_source_hash": kernel_source_hash(), "tile": tile_dict(tile)}
     cf, _ = _median_counter(cfetch, "FETCH_SIZE", "k_ceil_copy")
