@@ -611,9 +611,9 @@ def ceilings(dev, reps: int = 10):
                         "wave_instr_per_clk_per_cu": lane_ops / 64 / (ms * 1e-3) / (CUS * ENGINE_CLOCK_HZ),
                         "ms": ms}
     iters_r = 2048
-    for form, name in ((0, "cas64_pairs"), (1, "native_ds_add_f32")):
+    for form, name in ((0, "cas64_pairs"), (1, "native_ds_add_f32"), (2, "native_ds_add_f64")):
         ms = timed(lambda: L.gcp_ceiling_lds_row_adds(form, iters_r, grid, C.c_void_p(sink.data_ptr()), st))
-        out.setdefault("lds_row_adds", {})[name] = {"float_adds_per_s": grid * 1024 * iters_r * 4 / (ms * 1e-3),
+        out.setdefault("lds_row_adds", {})[name] = {"adds_per_s": grid * 1024 * iters_r * 4 / (ms * 1e-3),
                                                     "ms": ms}
     Gr = torch.zeros(sum(DIMS) * RANK, dtype=torch.float32, device=dev)
     nup = 1 << 22
@@ -632,7 +632,7 @@ def ceilings(dev, reps: int = 10):
     t_draw = n / out["dependent_record_3_row_gathers"]["samples_per_s"]
     t_write = n * d * ent_bytes / copy_bps
     t_owner_gather = n * d * 2 / out["streamed_record_3_row_gathers"]["rows_per_s"]
-    t_owner_cas = n * d * RANK / out["lds_row_adds"]["cas64_pairs"]["float_adds_per_s"]
+    t_owner_cas = n * d * RANK / out["lds_row_adds"]["cas64_pairs"]["adds_per_s"]
     t_read = n * d * ent_bytes / copy_bps
     parts_a = {"dependent record and row gathers": t_draw, "sort-entry writes": t_write}
     parts_b = {"streamed-entry row gathers": t_owner_gather, "LDS compare-and-swap adds": t_owner_cas,

@@ -42,12 +42,13 @@ gcp_status gcp_ceiling_dependent_gathers(const void* rec, int64_t nrec, const fl
  * LDS per workgroup).  sink: device scratch of >= 4 * grid bytes. */
 gcp_status gcp_ceiling_lds_cas(int iters, int block, int grid, void* sink, hipStream_t stream);
 
-/* grid workgroups of 1024 threads, each with a 32 KB LDS block of 256 rows
- * x 32 floats; every iteration each group of 8 lanes picks a row at random
- * and each lane adds 4 floats to its 4 columns (4 * iters float adds per
- * lane).  form 0: two 64-bit compare-and-swap float-pair loops per lane;
- * form 1: four native LDS float atomic adds.  sink: device scratch of
- * >= 4 * grid bytes. */
+/* grid workgroups of 1024 threads, each with an LDS block of 256 rows x 32
+ * values; every iteration each group of 8 lanes picks a row at random and
+ * each lane adds 4 values to its 4 columns (4 * iters adds per lane).
+ * form 0: float block (32 KB), two 64-bit compare-and-swap float-pair loops
+ * per lane; form 1: float block, four native LDS float atomic adds; form 2:
+ * double block (64 KB), four native LDS double atomic adds.  sink: device
+ * scratch of >= 4 * grid bytes. */
 gcp_status gcp_ceiling_lds_row_adds(int form, int iters, int grid, void* sink, hipStream_t stream);
 
 /* nupdates requests of 32 float atomic adds (one 128-byte row) at

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gcp_internal.hpp"
 
 namespace gcp {
@@ -129,9 +131,10 @@ __global__ void __launch_bounds__(1024) k_ceil_lds_cas(int iters, float* __restr
 }
 
 // Eight lanes per row: every iteration each group of 8 lanes draws a row of
-// the 256 x 32 float block (32 KB of LDS) and each lane adds 4 floats to its
-// 4 columns.  FORM 0: two 64-bit compare-and-swap float-pair loops (the
-// owner pass's form); FORM 1: four native LDS float atomic adds.
+// the 256 x 32 block and each lane adds 4 values to its 4 columns.  FORM 0:
+// float block (32 KB of LDS), two 64-bit compare-and-swap float-pair loops
+// (the owner pass's form); FORM 1: float block, four native LDS float atomic
+// adds; FORM 2: double block (64 KB), four native LDS double atomic adds.
 __device__ __forceinline__ uint32_t hmix32(uint32_t x)
 {
     // 32-bit integer finaliser (xorshift-multiply), cheap next to the adds
@@ -146,14 +149,15 @@ __device__ __forceinline__ uint32_t hmix32(uint32_t x)
 template <int FORM>
 __global__ void __launch_bounds__(1024) k_ceil_lds_rows(int iters, float* __restrict__ sink)
 {
-    __shared__ __attribute__((aligned(16))) float blk[256 * 32];
-    for (int e = threadIdx.x; e < 256 * 32; e += blockDim.x) blk[e] = 0.f;
+    using V = typename std::conditional<FORM == 2, double, float>::type;
+    __shared__ __attribute__((aligned(16))) V blk[256 * 32];
+    for (int e = threadIdx.x; e < 256 * 32; e += blockDim.x) blk[e] = V(0);
     __syncthreads();
     const uint32_t grp = threadIdx.x >> 3;
     const int c4 = (threadIdx.x & 7) * 4;
     for (int it = 0; it < iters; ++it) {
         const uint32_t row = hmix32(blockIdx.x * 0x9e3779b9u + grp * 0x85ebca6bu + (uint32_t)it * 0xc2b2ae35u) & 255u;
-        float* p = blk + row * 32 + c4;
+        V* p = blk + row * 32 + c4;
         if constexpr (FORM == 0) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -172,11 +176,11 @@ __global__ void __launch_bounds__(1024) k_ceil_lds_rows(int iters, float* __rest
         } else {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                __hip_atomic_fetch_add(p + v, 1.0f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(p + v, V(1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && blk[0] == -1.f) sink[blockIdx.x] = 1.f;
+    if (threadIdx.x == 0 && blk[0] == V(-1)) sink[blockIdx.x] = 1.f;
 }
 
 // Groups of 32 lanes add one float each to a random row of 32 floats.
@@ -267,12 +271,14 @@ gcp_status gcp_ceiling_lds_cas(int iters, int block, int grid, void* sink, hipSt
 gcp_status gcp_ceiling_lds_row_adds(int form, int iters, int grid, void* sink, hipStream_t stream)
 {
     clear_error();
-    if (!sink || iters < 1 || grid < 1 || (form != 0 && form != 1))
+    if (!sink || iters < 1 || grid < 1 || form < 0 || form > 2)
         return set_error(GCP_ERR_ARG, "gcp_ceiling_lds_row_adds arguments");
     if (form == 0)
         hipLaunchKernelGGL(k_ceil_lds_rows<0>, dim3((unsigned)grid), dim3(1024), 0, stream, iters, (float*)sink);
-    else
+    else if (form == 1)
         hipLaunchKernelGGL(k_ceil_lds_rows<1>, dim3((unsigned)grid), dim3(1024), 0, stream, iters, (float*)sink);
+    else
+        hipLaunchKernelGGL(k_ceil_lds_rows<2>, dim3((unsigned)grid), dim3(1024), 0, stream, iters, (float*)sink);
     GCP_HIP(hipGetLastError());
     return GCP_OK;
 }

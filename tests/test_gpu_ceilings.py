@@ -55,11 +55,11 @@ def test_rate_kernels_run_on_small_sizes(gpu):
         G._check(L.gcp_ceiling_dependent_gathers(C.c_void_p(rec.data_ptr()), 1000, C.c_void_p(A.data_ptr()), dims3,
                                                  5000, seq, 256, s, st), "gathers")
     G._check(L.gcp_ceiling_lds_cas(16, 256, 8, s, st), "lds cas")
-    for form in (0, 1):
+    for form in (0, 1, 2):
         G._check(L.gcp_ceiling_lds_row_adds(form, 16, 8, s, st), "lds row adds")
     torch.cuda.synchronize()
     assert L.gcp_ceiling_random_reads(C.c_void_p(rec.data_ptr()), 1000, 10, 2, 256, s, st) == G.GCP_ERR_ARG
-    assert L.gcp_ceiling_lds_row_adds(2, 16, 8, s, st) == G.GCP_ERR_ARG
+    assert L.gcp_ceiling_lds_row_adds(3, 16, 8, s, st) == G.GCP_ERR_ARG
     assert L.gcp_ceiling_lds_cas(16, 100, 8, s, st) == G.GCP_ERR_ARG
     assert L.gcp_ceiling_copy(C.c_void_p(rec.data_ptr()), s, 10, st) == G.GCP_ERR_ARG
     bad = (C.c_int64 * 3)(30, 0, 10)
