@@ -139,21 +139,11 @@ using BAKernel = void (*)(const LGParams<T>);
     X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(64, 2) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4)
 #define GCP_LG_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(4, 2) X(8, 2) X(16, 2) X(32, 2) X(64, 2) X(64, 4)
 
-// The general-order (D = 0) float64 kernel with 64 lanes of one column is not
-// built: this toolchain fails to generate code for it on gfx950.  Even R uses
-// 32 lanes of two columns instead.
-template <typename T, int D, int LN, int VC>
-constexpr bool shape_built()
-{
-    return !(D == 0 && sizeof(T) == 8 && LN == 64 && VC == 1);
-}
-
 template <typename T, int D, int SRC>
 inline LGKernel<T> pick_shape(int lanes, int vec)
 {
-#define GCP_CASE(LN, VC)                                          \
-    if constexpr (shape_built<T, D, LN, VC>())                    \
-        if (lanes == LN && vec == VC) return k_loss_grad<T, D, LN, VC, SRC>;
+#define GCP_CASE(LN, VC) \
+    if (lanes == LN && vec == VC) return k_loss_grad<T, D, LN, VC, SRC>;
     if constexpr (sizeof(T) == 4) {
         GCP_LG_SHAPES_F32(GCP_CASE)
     } else {

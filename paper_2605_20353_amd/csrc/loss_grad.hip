@@ -239,6 +239,8 @@ static gcp_status launch_loss_grad(const gcp_tensor_s* t, const gcp_sample_param
     if (R % vec != 0) return set_error(GCP_ERR_ARG, "vec = %d does not divide R = %d", vec, R);
     if (lanes * vec < R) return set_error(GCP_ERR_ARG, "lanes*vec = %d < R = %d", lanes * vec, R);
     const int src = write_y ? 2 : smp ? (given_values ? 3 : 1) : 0;
+    // the general-order float64 kernel with 64 lanes of one column needs 128
+    // VGPRs and spills; even R takes 32 lanes of two columns instead
     if (sizeof(T) == 8 && kernel_order(t) == 0 && lanes == 64 && vec == 1 && R % 2 == 0 && !(tile && tile->lanes > 0)) {
         lanes = 32;
         vec = 2;

@@ -40,6 +40,9 @@ CASES = {
     "1way": ([300], 40, 4),
     "r32": ([64, 48, 40], 2000, 32),
     "r64_4way": ([30, 20, 16, 8], 900, 64),
+    "8way": ([3, 4, 2, 5, 3, 2, 4, 3], 500, 4),          # the most modes a tensor may have
+    "r1_unit_mode": ([40, 1, 30], 300, 1),              # rank 1, and a mode of one index (no key bits)
+    "5way_r33": ([6, 5, 4, 3, 7], 200, 33),             # general order, odd rank: 64 lanes of one column
 }
 
 
@@ -270,7 +273,7 @@ def _shapes(R, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("name", ["r32", "r64_4way", "cfg1_50x40x30"])
+@pytest.mark.parametrize("name", ["r32", "r64_4way", "cfg1_50x40x30", "8way", "r1_unit_mode"])
 def test_every_tile_matches_oracle(gpu, dtype, name):
     t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
     A = model(dims, R, dtype, gpu)
