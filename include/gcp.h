@@ -177,13 +177,15 @@ const char* gcp_last_error(void);
 int64_t gcp_struct_size(const char* name);
 
 /* Sparse COO tensor (Sec. 3.1.1: N coordinate tuples and N values).
- * dims_host: d host int64 mode sizes (1 <= d <= 8, I_k >= 1, sum_k
- * ceil(log2 I_k) <= 63 and sum_k I_k < 2^32 model rows, else
- * GCP_ERR_UNSUPPORTED).  coords_dev: device int64 [nnz x d]; vals_dev:
- * device values of dtype dt.  Copies and packs the nonzeros into 16-byte
- * device records and builds an open-addressing hash table of the packed
- * coordinates (the O(1) membership search of Sec. 3.1.1; the smallest power
- * of two >= 4 nnz slots of 8 bytes, at least 2^10).  The inputs may be
+ * dims_host: d host int64 mode sizes (1 <= d <= 8 and I_k >= 1, else
+ * GCP_ERR_ARG; each I_k < 2^32, sum_k I_k < 2^32 model rows and
+ * prod_k I_k < 2^64 - 1 cells, else GCP_ERR_UNSUPPORTED).  coords_dev:
+ * device int64 [nnz x d]; vals_dev: device values of dtype dt.  Copies and
+ * packs the nonzeros into 16-byte device records {cell key, value} -- the
+ * key is the bit-packed coordinates when sum_k ceil(log2 I_k) <= 63, else
+ * the row-major linear index -- and builds an open-addressing hash table of
+ * the keys (the O(1) membership search of Sec. 3.1.1; the smallest power of
+ * two >= 4 nnz slots of 8 bytes, at least 2^10).  The inputs may be
  * freed after the call returns.  Synchronises the stream: repeated or
  * out-of-range coordinates return GCP_ERR_DATA.  The handle owns its device
  * memory until gcp_tensor_destroy. */
