@@ -133,7 +133,9 @@ typedef struct gcp_tile {
     int32_t bucket_lds_bytes;     /* LDS bytes of one row block (rows are a
                                      power of two); 0 = 32768, min 8192     */
     int32_t bucket_block_samples; /* samples sorted per workgroup, multiple
-                                     of 64 in [512, 8192]; 0 = 2048          */
+                                     of 64 in [512, 8192]; 0 = 2048, halved
+                                     while that leaves fewer than two
+                                     workgroups per CU                       */
     int32_t bucket_splits;        /* workgroups per row block (each reads
                                      ceil(J / bucket_splits) of the J sort
                                      segments); 0 = auto                    */
@@ -152,8 +154,8 @@ typedef struct gcp_tile {
                                    tile and device: the sampled tensor is
                                    written, its (row, sample) pairs sorted by
                                    row (a stable radix sort), and each gradient
-                                   row summed by one wavefront in an order
-                                   fixed by its sorted run;
+                                   row with pairs summed by one lane group in
+                                   the order of its sorted run;
                                    the objective's per-wavefront partial sums
                                    are added in a fixed order.  Drawn samples
                                    only (smp must be NULL); needs the workspace
