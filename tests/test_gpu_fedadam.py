@@ -326,6 +326,25 @@ def test_fp64_four_way_rounds_match_oracle(gpu, scatter):
         assert _rel(cl.M.cpu().numpy(), oc.M) <= 1e-10
 
 
+@pytest.mark.parametrize("scatter", ["atomic", "bucketed"])
+def test_fp32_four_way_rounds_match_oracle(gpu, scatter):
+    """4-way client blocks in FP32 (the general-order kernels of both batched
+    forms at rank 16) against the oracle's rounds: U, every M_c, B_c, C_c."""
+    gdims, R = [40, 36, 24, 16], 16
+    blocks = _blocks(gdims, (2, 2, 1, 2), R, 200, 900, seed=2616)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2716, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=600, q=500, seed=8, lr=1e-3, meta_lr=1e-3, lower=0.0)
+    tile = FedTile() if scatter == "atomic" else FedTile(lds_modes=0, bucket_modes=15, bucket_block_samples=512)
+    say(f"fedadam fp32 4-way {scatter}")
+    fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg, tile=tile)
+    assert fed.info()["form"] == ("persistent" if scatter == "atomic" else "row_bucketed")
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"4-way {scatter}")
+
+
 def test_batched_and_plain_classes_equal_the_flags(gpu):
     from paper_2605_20353_amd.fedadam import Batched, Plain
     gdims, R = SMALL["gdims"], SMALL["R"]
