@@ -1,10 +1,11 @@
 """GCP_DETERMINISTIC: the sampled gradient and objective are bit-identical on
 repeated runs (the sampled tensor written, its (row, sample) pairs sorted by
-row with a stable sort, each gradient row summed by one wavefront in an order
-fixed by the sorted run, the objective's per-wavefront partials added in slot
+row with a stable sort, each gradient row summed by one lane group in an
+order fixed by the sorted run, the objective's per-wavefront partials added in slot
 order), and they are the oracle's gradient and objective within the rounding
-bound, for every loss, tensors of 1, 3, 4 and 5 modes, ranks 4 to 96, both
-dtypes, with scale and accumulation."""
+bound, for every loss and sampling scheme (stratified, semi-stratified,
+uniform over a dense tensor), tensors of 1, 3, 4 and 5 modes, ranks 4 to 96,
+both dtypes, with scale and accumulation."""
 import sys
 
 import numpy as np
@@ -85,6 +86,47 @@ def test_deterministic_ranks_and_orders(gpu, dtype, dims, R, nnz):
     assert_grad_close(G1.cpu().numpy(), Go, dims, R, A64, sc, sx, sw, "poisson", dtype,
                       what=f"deterministic dims={dims} R={R}")
     assert abs(L1.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_deterministic_semi_stratified_and_uniform(gpu, dtype):
+    """The other two sampling schemes through the bit-reproducible form:
+    semi-stratified samples (y = w (f'(x, m) - f'(0, m)) for the nonzeros) of
+    a sparse tensor, and uniform samples of a dense one."""
+    dims, R = [300, 200, 100], 16
+    t, to = _case(gpu, dtype, dims, 6000, False, seed=2665)
+    A = (0.2 + 0.8 * synth.init_model(dims, R, 13, dtype=torch.float64)).to(dtype).to(gpu)
+    sp = G.SampleParams("semi_stratified", 4000 + 5, 3000 + 2, seed=21, step=3)
+    t.reserve(sp.n, R)
+    say(f"deterministic semi-stratified {dtype}")
+    G1, L1 = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
+    G2, L2 = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
+    t.status()
+    assert torch.equal(G1, G2) and torch.equal(L1, L2), "semi-stratified runs differ"
+    sc, sx, sw = oracle.sample_stratified(to, sp.p, sp.q, sp.seed, sp.step, semi=True)
+    A64 = A.double().cpu().numpy().reshape(-1)
+    Go, Fo = oracle.loss_grad(dims, R, A64, sc, sx, sw, "poisson", n_semi=sp.p)
+    assert_grad_close(G1.cpu().numpy(), Go, dims, R, A64, sc, sx, sw, "poisson", dtype, n_semi=sp.p,
+                      what="deterministic semi-stratified")
+    assert abs(L1.item() - Fo) <= TOL[dtype] * abs(Fo)
+
+    ddims, dR = [20, 18, 16, 12], 8
+    X, _ = synth.dense_gaussian(ddims, 4, seed=6, dtype=torch.float64)
+    td = G.DenseTensor(ddims, X.to(dtype).to(gpu))
+    Ad = (0.5 * synth.init_model(ddims, dR, 17, dist="normal", dtype=torch.float64)).to(dtype).to(gpu)
+    spu = G.SampleParams("uniform", 6000 + 7, 0, seed=23, step=1)
+    td.reserve(spu.n, dR)
+    say(f"deterministic uniform {dtype}")
+    H1, M1 = G.gcp_loss_grad(td, spu, Ad, dR, "gaussian", deterministic=True)
+    H2, M2 = G.gcp_loss_grad(td, spu, Ad, dR, "gaussian", deterministic=True)
+    td.status()
+    assert torch.equal(H1, H2) and torch.equal(M1, M2), "uniform runs differ"
+    uc, ux, uw = oracle.sample_uniform(ddims, X.to(dtype).double().numpy(), spu.p, spu.seed, spu.step)
+    Ad64 = Ad.double().cpu().numpy().reshape(-1)
+    Ho, Mo = oracle.loss_grad(ddims, dR, Ad64, uc, ux, uw, "gaussian")
+    assert_grad_close(H1.cpu().numpy(), Ho, ddims, dR, Ad64, uc, ux, uw, "gaussian", dtype,
+                      what="deterministic uniform")
+    assert abs(M1.item() - Mo) <= TOL[dtype] * abs(Mo)
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
