@@ -46,3 +46,78 @@ def test_small_steps_are_accepted_and_lower_the_objective():
     assert fails == 0 and rates == [1e-3] * 3 and len(objs) == 4
     assert all(b < a for a, b in zip(objs, objs[1:]))
     assert np.abs(A - A0.reshape(-1)).max() > 0
+
+
+def test_epochs_equal_an_independent_implementation():
+    """The whole trajectory -- objectives of the accepted epochs, the rate of
+    every epoch, the undone epochs and the final model -- equals a separate
+    implementation that shares only the (separately pinned) sampler with the
+    oracle: gradients by torch.autograd of the weighted Gaussian objective,
+    torch.optim.Adam with eps = 0 (where its update is Alg. adam-update's;
+    every factor row is sampled in every iteration on this 3 x 3 x 3 tensor,
+    so no second moment is zero), and the restore-and-decay loop of the
+    paper's experiments written out here with optimizer state snapshots."""
+    import copy
+
+    import torch
+
+    dims, R = [3, 3, 3], 2
+    data = synth.count_tensor(dims, R, 10, seed=21)
+    t = oracle.SparseTensor(dims, data.coords.numpy(), data.vals.numpy())
+    A0 = (0.3 + synth.init_model(dims, R, 22)).numpy()
+    p = q = 30
+    obj_p = obj_q = 100
+    iters, max_epochs, lr, decay, max_fails, seed, oc = 4, 8, 4.0, 0.5, 3, 13, 1 << 62
+    ap = oracle.AdamParams(eps=0.0, lower=-np.inf)
+    A_o, objs_o, rates_o, fails_o = oracle.gcp_adam_epochs(t, R, A0, "gaussian", p, q, obj_p, obj_q, iters,
+                                                           max_epochs, lr, decay, max_fails, seed=seed,
+                                                           obj_client=oc, ap=ap)
+
+    offs = np.cumsum([0] + dims)
+    A = torch.tensor(A0.reshape(-1), dtype=torch.float64, requires_grad=True)
+
+    def F(c, x, w):
+        M = A.view(sum(dims), R)
+        prod = torch.ones(len(x), R, dtype=torch.float64)
+        for k in range(len(dims)):
+            prod = prod * M[torch.as_tensor(offs[k] + c[:, k])]
+        m = prod.sum(1)
+        return (torch.as_tensor(w) * 0.5 * (m - torch.as_tensor(x)) ** 2).sum()
+
+    def objective():
+        c, x, w = oracle.sample_stratified(t, obj_p, obj_q, seed, 0, oc)
+        with torch.no_grad():
+            return float(F(c, x, w))
+
+    opt = torch.optim.Adam([A], lr=lr, betas=(ap.beta1, ap.beta2), eps=0.0)
+    f_prev = objective()
+    objs, rates, fails, it, rate = [f_prev], [], 0, 0, lr
+    for _ in range(max_epochs):
+        saved = (A.detach().clone(), copy.deepcopy(opt.state_dict()))
+        for _ in range(iters):
+            c, x, w = oracle.sample_stratified(t, p, q, seed, it, 0)
+            it += 1
+            opt.zero_grad()
+            F(c, x, w).backward()
+            assert torch.count_nonzero(A.grad).item() == A.numel()
+            opt.step()
+        f = objective()
+        rates.append(rate)
+        if f < f_prev:
+            f_prev = f
+            objs.append(f)
+        else:
+            with torch.no_grad():
+                A.copy_(saved[0])
+            opt.load_state_dict(saved[1])
+            rate *= decay
+            for g in opt.param_groups:
+                g["lr"] = rate
+            fails += 1
+            if fails >= max_fails:
+                break
+    assert fails == fails_o and rates == rates_o
+    assert 0 < fails < max_fails and len(rates) == max_epochs   # epochs undone, decayed, then accepted again
+    assert len(objs) == len(objs_o) > 1
+    np.testing.assert_allclose(objs, objs_o, rtol=1e-10)
+    np.testing.assert_allclose(A.detach().numpy(), A_o, rtol=1e-9, atol=1e-12)
