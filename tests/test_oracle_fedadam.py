@@ -98,3 +98,73 @@ def test_round_resets_clients_and_keeps_their_moments():
             assert not np.array_equal(cl.B, b)
     assert st == 2
     assert all(cl.t == 4 for cl in clients)
+
+
+def test_rounds_equal_an_independent_implementation():
+    """Two rounds of three local steps equal a separate implementation that
+    shares only the (separately pinned) sampler with the oracle: each client
+    a torch tensor with its own torch.optim.Adam (state kept across rounds,
+    the model reset to the server rows each round), gradients by
+    torch.autograd of the client's weighted Gaussian objective in block
+    coordinates, the per-row mean of U - M_c over the covering clients, and a
+    server torch.optim.Adam at the meta-rate; eps = 0 on both sides (every
+    row of every block is sampled in every step here, so no second moment is
+    zero).  U, every M_c and the client moments must agree."""
+    import torch
+
+    gdims, grid, R = [6, 4, 6], (2, 1, 2), 2
+    clients, U = _setup(gdims, grid, R, seed=5)
+    U0 = U.copy()
+    p = q = 20
+    seed, tau, rounds, lr, meta = 23, 3, 2, 0.05, 0.1
+    cap = oracle.AdamParams(lr=lr, eps=0.0, lower=-np.inf)
+    sap = oracle.AdamParams(lr=meta, eps=0.0, lower=-np.inf)
+    Bs, Cs = np.zeros_like(U), np.zeros_like(U)
+    st = 0
+    for r in range(rounds):
+        st = oracle.fedadam_round(clients, gdims, R, U, Bs, Cs, st, r, tau, "gaussian", p, q, seed, cap, sap)
+
+    goff = np.concatenate([[0], np.cumsum(gdims)])
+    Ut = torch.tensor(U0, dtype=torch.float64, requires_grad=True)
+    sopt = torch.optim.Adam([Ut], lr=meta, betas=(sap.beta1, sap.beta2), eps=0.0)
+    Ms, opts = [], []
+    for cl in clients:
+        Mc = torch.zeros(int(sum(cl.tensor.dims)) * R, dtype=torch.float64, requires_grad=True)
+        Ms.append(Mc)
+        opts.append(torch.optim.Adam([Mc], lr=lr, betas=(cap.beta1, cap.beta2), eps=0.0))
+
+    def F(Mc, dims, c, x, w):
+        loff = np.concatenate([[0], np.cumsum(dims)])
+        M2 = Mc.view(-1, R)
+        prod = torch.ones(len(x), R, dtype=torch.float64)
+        for k in range(len(dims)):
+            prod = prod * M2[torch.as_tensor(loff[k] + c[:, k])]
+        return (torch.as_tensor(w) * 0.5 * (prod.sum(1) - torch.as_tensor(x)) ** 2).sum()
+
+    for r in range(rounds):
+        Dsum = torch.zeros(int(sum(gdims)), R, dtype=torch.float64)
+        count = torch.zeros(int(sum(gdims)), dtype=torch.float64)
+        for c, cl in enumerate(clients):
+            rows = torch.as_tensor(_client_rows(gdims, cl, R))
+            with torch.no_grad():
+                Ms[c].copy_(Ut.view(-1, R)[rows].reshape(-1))
+            for j in range(tau):
+                sc, sx, sw = oracle.sample_stratified(cl.tensor, p, q, seed, step=r * tau + j, client=c)
+                opts[c].zero_grad()
+                F(Ms[c], cl.tensor.dims, sc, sx, sw).backward()
+                assert torch.count_nonzero(Ms[c].grad).item() == Ms[c].numel()
+                opts[c].step()
+            with torch.no_grad():
+                Dsum[rows] += Ut.view(-1, R)[rows] - Ms[c].view(-1, R)
+                count[rows] += 1
+        Ut.grad = (Dsum / count[:, None]).reshape(-1)
+        sopt.step()
+
+    np.testing.assert_allclose(Ut.detach().numpy(), U, rtol=1e-10, atol=1e-13)
+    for c, cl in enumerate(clients):
+        np.testing.assert_allclose(Ms[c].detach().numpy(), cl.M, rtol=1e-10, atol=1e-13)
+        state = opts[c].state[Ms[c]]
+        np.testing.assert_allclose(state["exp_avg"].numpy(), cl.B, rtol=1e-10, atol=1e-15)
+        np.testing.assert_allclose(state["exp_avg_sq"].numpy(), cl.C, rtol=1e-10, atol=1e-15)
+    assert st == rounds and all(cl.t == rounds * tau for cl in clients)
+    assert np.abs(U - U0).max() > 1e-3                     # the server model moved
