@@ -330,8 +330,8 @@ using FedKernel = void (*)(const FedArgs<T>);
 template <typename T>
 using FedStepKernel = void (*)(const FedArgs<T>, int);
 
-#define GCP_FED_SHAPES_F32(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(16, 2) X(32, 2) X(8, 4) X(16, 4)
-#define GCP_FED_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(16, 2) X(32, 2)
+#define GCP_FED_SHAPES_F32(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(16, 2) X(32, 2) X(64, 2) X(8, 4) X(16, 4) X(64, 4)
+#define GCP_FED_SHAPES_F64(X) X(8, 1) X(16, 1) X(32, 1) X(64, 1) X(16, 2) X(32, 2) X(64, 2) X(64, 4)
 
 template <typename T, int D>
 static FedKernel<T> pick_fed(int lanes, int vec)
@@ -835,10 +835,13 @@ gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_
     f->block = D.block > 0 ? D.block : (f->want_bucket ? 1024 : 256);
     if (f->block % 64 != 0 || f->block > 1024) { delete f; return set_error(GCP_ERR_ARG, "block = %d", f->block); }
     // lane shape: one column per lane up to R = 64 (coalesced gradient
-    // atomics); with the row-bucketed scatter, which issues no gradient
-    // atomics for its modes, four columns per lane in FP32
+    // atomics), else the fewest columns per lane that let 64 lanes cover R;
+    // with the row-bucketed scatter, which issues no gradient atomics for its
+    // modes, four columns per lane in FP32
     const bool wide = f->want_bucket && f->dt == GCP_F32 && D.R % 4 == 0 && D.R <= 64;
-    f->vec = D.vec > 0 ? D.vec : wide ? 4 : (D.R > 64 && D.R % 2 == 0 ? 2 : 1);
+    int vec_auto = 1;
+    while (vec_auto < 4 && 64 * vec_auto < D.R) vec_auto *= 2;
+    f->vec = D.vec > 0 ? D.vec : wide ? 4 : vec_auto;
     if (D.lanes > 0) f->lanes = D.lanes;
     else if (wide && D.vec <= 0) f->lanes = D.R <= 32 ? 8 : 16;
     else {

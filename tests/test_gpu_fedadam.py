@@ -345,6 +345,28 @@ def test_fp32_four_way_rounds_match_oracle(gpu, scatter):
     _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"4-way {scatter}")
 
 
+@pytest.mark.parametrize("dtype,R", [(torch.float64, 48), (torch.float64, 100), (torch.float64, 200),
+                                     (torch.float32, 96), (torch.float32, 256)])
+@pytest.mark.parametrize("scatter", ["atomic", "bucketed"])
+def test_wide_rank_rounds_match_oracle(gpu, dtype, R, scatter):
+    """Ranks past 32 (FP64) and 64 (FP32): 64 lanes of 1, 2 or 4 columns in
+    both batched forms against the oracle's rounds."""
+    gdims = SMALL["gdims"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2617)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2717, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=64, q=64, seed=20353, lr=1e-2, meta_lr=1e-2, lower=0.0)
+    tile = FedTile() if scatter == "atomic" else FedTile(lds_modes=0, bucket_modes=7, bucket_block_samples=512)
+    say(f"fedadam wide rank R={R} {dtype} {scatter}")
+    fed = FedAdam(_gpu_clients(blocks, dtype, gpu), gdims, U0.to(dtype).to(gpu), cfg, tile=tile)
+    info = fed.info()
+    assert info["lanes"] == 64 and info["lanes"] * info["vec"] >= R, info
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(dtype), cfg, 2, dtype)
+    _assert_state_matches(fed, Uo, ocl, 1e-10 if dtype == torch.float64 else FP32_TOL, f"R={R} {scatter}")
+
+
 def test_batched_and_plain_classes_equal_the_flags(gpu):
     from paper_2605_20353_amd.fedadam import Batched, Plain
     gdims, R = SMALL["gdims"], SMALL["R"]
