@@ -114,7 +114,9 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
     const int c = blockIdx.x / F.W, w = blockIdx.x % F.W;
     const FedClientDev<T>& C = F.clients[c];
     // a private copy: read once, then held in registers -- read through the
-    // global reference, every field would be reloaded after each atomic
+    // global reference, every field would be reloaded after each atomic.  It
+    // stays in registers only while every index into it is a compile-time one
+    constexpr int DM = D > 0 ? D : kMaxModes;
     const LGParams<T> P = C.P;
     T* M = const_cast<T*>(P.A);
     T* G = P.G;
@@ -153,8 +155,9 @@ __global__ void __launch_bounds__(1024) k_fed_clients(const FedArgs<T> F)
         if (P.lds_mask) {
             // flush this workgroup's share of the small modes' gradient once
             __syncthreads();
-            for (int k = 0; k < dd; ++k) {
-                if (!((P.lds_mask >> k) & 1u)) continue;
+#pragma unroll
+            for (int k = 0; k < DM; ++k) {
+                if (k >= dd || !((P.lds_mask >> k) & 1u)) continue;
                 const int64_t elems = P.sc.L.dims[k] * (int64_t)P.R;
                 T* dst = G + P.rowoff[k] * P.R;
                 const T* src = priv + P.lds_off[k];

@@ -631,7 +631,7 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
             nxt[u] = e < cnt ? seg[e] : make_uint4(0, 0, 0, 0);
         }
         for (int base = 0; base < cnt; base += S * U) {
-            uint64_t key[U];
+            uint32_t ik[U];
             T y[U];
             T a[U][DM][VEC];
 #pragma unroll
@@ -641,9 +641,14 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
                 const uint4 ent = nxt[u];
                 const int en = e + S * U;
                 nxt[u] = en < cnt ? seg[en] : make_uint4(0, 0, 0, 0);
-                key[u] = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
+                const uint64_t key = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
                 uint32_t ci[DM];
-                unpack_all<D == 0>(P.sc.L, dd, key[u], ci);
+                unpack_all<D == 0>(P.sc.L, dd, key, ci);
+                // the owned mode's row, picked with compile-time indices
+                ik[u] = ci[0];
+#pragma unroll
+                for (int kk = 1; kk < DM; ++kk)
+                    if (kk == k) ik[u] = ci[kk];
                 y[u] = valid ? entry_y<T>(ent) : T(0);
 #pragma unroll
                 for (int kk = 0; kk < DM; ++kk) {
@@ -662,10 +667,7 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
             for (int u = 0; u < U; ++u) {
                 const int e = base + u * S + g;
                 if (e >= cnt || !col_ok) continue;
-                uint32_t i;
-                if constexpr (D == 0) i = unpack_one<true, DM>(P.sc.L, dd, key[u], k);
-                else i = (uint32_t)((key[u] >> shift_k) & mask_k);
-                i -= (uint32_t)r0;
+                const uint32_t i = ik[u] - (uint32_t)r0;
                 T c[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {

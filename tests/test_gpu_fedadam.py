@@ -345,6 +345,32 @@ def test_fp32_four_way_rounds_match_oracle(gpu, scatter):
     _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"4-way {scatter}")
 
 
+@pytest.mark.parametrize("gdims,grid", [([60, 48], (2, 2)), ([12, 10, 8, 8, 6], (2, 1, 2, 1, 2))],
+                         ids=["2-way", "5-way"])
+@pytest.mark.parametrize("scatter", ["atomic", "bucketed", "lds_and_bucketed"])
+def test_fp32_two_and_five_way_rounds_match_oracle(gpu, gdims, grid, scatter):
+    """Orders 2 and 5 through the general-order kernels of both batched forms
+    in FP32; the 5-way blocks draw their fifth coordinate from the second
+    Philox block of each counter."""
+    R = 8
+    d = len(gdims)
+    blocks = _blocks(gdims, grid, R, 60, 300, seed=2618 + d)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2718 + d, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=300, q=200, seed=9, lr=1e-3, meta_lr=1e-3, lower=0.0)
+    full = (1 << d) - 1
+    tile = {"atomic": FedTile(),
+            "bucketed": FedTile(lds_modes=0, bucket_modes=full, bucket_block_samples=512),
+            "lds_and_bucketed": FedTile(lds_modes=1, bucket_modes=full & ~1, bucket_block_samples=512)}[scatter]
+    say(f"fedadam fp32 {d}-way {scatter}")
+    fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg, tile=tile)
+    assert fed.info()["form"] == ("persistent" if scatter == "atomic" else "row_bucketed")
+    for r in range(2):
+        fed.round(r)
+    fed.status()
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"{d}-way {scatter}")
+
+
 @pytest.mark.parametrize("dtype,R", [(torch.float64, 48), (torch.float64, 100), (torch.float64, 200),
                                      (torch.float32, 96), (torch.float32, 256)])
 @pytest.mark.parametrize("scatter", ["atomic", "bucketed"])
