@@ -371,6 +371,33 @@ def test_fp32_two_and_five_way_rounds_match_oracle(gpu, gdims, grid, scatter):
     _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"{d}-way {scatter}")
 
 
+def test_fp32_mixed_radix_client_blocks_match_oracle(gpu):
+    """Client blocks shaped like the Amazon tensor (4821207 x 1774269 x
+    1805187: 23 + 21 + 21 coordinate bits, so each block's cells take the
+    mixed-radix key) through both batched forms against the oracle's rounds
+    (one oracle run for both: its Adam over 3.4e7 client parameters per step
+    is the slow part)."""
+    gdims, R = [2 * 4821207, 1774269, 1805187], 4
+    blocks = _blocks(gdims, (2, 1, 1), R, 300, 600, seed=2619)
+    assert all(b.data.dims == [4821207, 1774269, 1805187] for b in blocks)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2719, dtype=torch.float64)
+    cfg = FedConfig(R=R, tau=2, loss="poisson", p=700, q=500, seed=10, lr=1e-3, meta_lr=1e-3, lower=0.0)
+    say("fedadam fp32 mixed-radix blocks: oracle")
+    Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(torch.float32), cfg, 2, torch.float32)
+    for scatter, tile in (("atomic", FedTile()),
+                          ("bucketed", FedTile(lds_modes=0, bucket_modes=7, bucket_block_samples=512))):
+        say(f"fedadam fp32 mixed-radix blocks {scatter}")
+        fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg, tile=tile)
+        assert fed.info()["form"] == ("persistent" if scatter == "atomic" else "row_bucketed")
+        for r in range(2):
+            fed.round(r)
+        fed.status()
+        _assert_state_matches(fed, Uo, ocl, FP32_TOL, f"mixed radix {scatter}")
+        fed.close()
+        del fed
+        torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("dtype,R", [(torch.float64, 48), (torch.float64, 100), (torch.float64, 200),
                                      (torch.float32, 96), (torch.float32, 256)])
 @pytest.mark.parametrize("scatter", ["atomic", "bucketed"])
