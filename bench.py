@@ -195,11 +195,21 @@ def _median_ms(fn, reps: int, warmup: int) -> float:
     return float(np.median(ts))
 
 
-def run_fedadam(dev, rounds: int, tune: bool = True):
-    """GCP-FedAdam, 64 clients on a 4x4x4 block grid over 20000x20000x2000,
-    1e5..5e6 nonzeros per client (log-uniform), rank 32 FP32, tau = 10 local
-    steps of 2^16 + 2^16 samples, then the server step.  Median ms per round
-    of four forms on the same state:
+# GCP-FedAdam workloads: global dims, client block grid, nonzeros per client
+# (log-uniform between the two), generator seed
+FED_WORKLOADS = {
+    "3way": ([20000, 20000, 2000], (4, 4, 4), 1e5, 5e6, 2610),
+    "4way": ([4000, 4000, 400, 100], (2, 2, 2, 2), 1e5, 1e6, 2610),
+}
+
+
+def run_fedadam(dev, rounds: int, tune: bool = True, workload: str = "3way"):
+    """GCP-FedAdam, by default 64 clients on a 4x4x4 block grid over
+    20000x20000x2000, 1e5..5e6 nonzeros per client (log-uniform); "4way" is
+    16 clients on a 2x2x2x2 grid over 4000x4000x400x100 with 1e5..1e6 (the
+    general-order kernels).  Rank 32 FP32, tau = 10 local steps of
+    2^16 + 2^16 samples, then the server step.  Median ms per round of four
+    forms on the same state:
       plain_atomic  per-client launches (a gcp_loss_grad and a gcp_adam_step
                     per client and local step), hardware-atomic scatter;
       plain_auto    per-client launches, each call's automatic scatter
@@ -212,9 +222,11 @@ def run_fedadam(dev, rounds: int, tune: bool = True):
                     autotuner's best row-bucketed shape.
     The speedup is the best batched form against the best per-client form,
     so the choice of scatter is not counted as a gain of batching."""
-    gd, grid, R = [20000, 20000, 2000], (4, 4, 4), 32
-    log("fedadam: generating 64 client blocks")
-    blocks = synth.fed_blocks(gd, grid, R, 1e5, 5e6, seed=2610, device=dev)
+    gd, grid, nnz_min, nnz_max, gseed = FED_WORKLOADS[workload]
+    R = 32
+    K = int(np.prod(grid))
+    log(f"fedadam: generating {K} client blocks")
+    blocks = synth.fed_blocks(gd, grid, R, nnz_min, nnz_max, seed=gseed, device=dev)
     nnz = sum(b.data.nnz for b in blocks)
     clients = [(G.SparseTensor(b.data.dims, b.data.coords, b.data.vals.to(torch.float32)), b.row_base)
                for b in blocks]
@@ -222,8 +234,9 @@ def run_fedadam(dev, rounds: int, tune: bool = True):
     U0 = synth.init_model(gd, R, 2710, device=dev, dtype=torch.float32)
     cfg = FedConfig(R=R, tau=10, loss="poisson", p=1 << 16, q=1 << 16, seed=SAMPLE_SEED, lr=1e-3, meta_lr=1e-3,
                     lower=0.0)
-    out = {"workload": "GCP-FedAdam, 64 clients (4x4x4 grid over 20000x20000x2000), "
-                       f"{nnz} nonzeros, rank 32 FP32, tau 10 x (2^16 + 2^16) samples per client",
+    out = {"workload": f"GCP-FedAdam, {K} clients ({'x'.join(map(str, grid))} grid over "
+                       f"{'x'.join(map(str, gd))}), {nnz} nonzeros, rank 32 FP32, tau 10 x (2^16 + 2^16) samples "
+                       "per client",
            "nnz": nnz, "forms": {}}
 
     def measure(name, fed):
@@ -256,7 +269,7 @@ def run_fedadam(dev, rounds: int, tune: bool = True):
     out["speedup_same_scatter"] = {
         "atomic (persistent vs plain_atomic)": f["plain_atomic"]["ms_per_round"] / f["persistent"]["ms_per_round"],
         "row-bucketed (bucketed vs plain_auto)": f["plain_auto"]["ms_per_round"] / f["bucketed"]["ms_per_round"]}
-    out["samples_per_round"] = 64 * 10 * (cfg.p + cfg.q)
+    out["samples_per_round"] = K * 10 * (cfg.p + cfg.q)
     out["batched_samples_per_s"] = out["samples_per_round"] / (out["batched_ms_per_round"] * 1e-3)
     log(f"fedadam: best per-client {best_plain} {out['plain_ms_per_round']:.2f} ms, best batched {best_batched} "
         f"{out['batched_ms_per_round']:.2f} ms per round -> {out['speedup']:.2f}x")
@@ -681,12 +694,16 @@ def main():
     ap.add_argument("--fedadam-only", action="store_true",
                     help="only run the GCP-FedAdam comparison (per-client vs batched round, the library's "
                          "automatic launch shape, no autotuning) and print its JSON")
+    ap.add_argument("--fed-workload", choices=sorted(FED_WORKLOADS), default="3way",
+                    help="GCP-FedAdam workload of --fedadam-only: 3way (64 clients over 20000x20000x2000) or 4way "
+                         "(16 clients over 4000x4000x400x100, the general-order kernels)")
     args = ap.parse_args()
     if args.ceilings:
         print(json.dumps(ceilings(torch.device("cuda:0"))))
         return
     if args.fedadam_only:
-        print(json.dumps(run_fedadam(torch.device("cuda:0"), args.fed_rounds, tune=False)))
+        print(json.dumps(run_fedadam(torch.device("cuda:0"), args.fed_rounds, tune=False,
+                                     workload=args.fed_workload)))
         return
     if args.hbm_resident:
         out = hbm_resident(torch.device("cuda:0"), args.hbm_nnz, max(1, min(args.steps, 50)), args.warmup)

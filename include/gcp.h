@@ -352,7 +352,13 @@ typedef struct gcp_fed_desc {
                                  and local step                                  */
     int32_t use_graph;        /* batched only: capture the round's launches into
                                  a HIP graph on the first round, replay after     */
-    int32_t workgroups_per_client; /* batched launch shape, 0 = automatic        */
+    int32_t workgroups_per_client; /* batched launch shape; 0 = automatic: the
+                                 persistent launch takes as many as stay
+                                 resident over K clients, at most enough for
+                                 about four 64-sample chunks per wavefront of
+                                 a local step; the row-bucketed sampling
+                                 launch as many as stay resident, at most one
+                                 per sample block                                */
     int32_t block;            /* threads per workgroup (batched), 0 = 256 (1024
                                  for row-bucketed rounds)                         */
     int32_t lanes;            /* lane shape of the gradient part, 0 = default    */

@@ -677,8 +677,12 @@ static gcp_status fed_build(gcp_fed_s* f)
         GCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f->client_kernel, f->block, f->client_lds));
         const int64_t resident = (int64_t)per_cu * device_cu_count(f->device);
         if (D.workgroups_per_client <= 0) {
-            // automatic: as many workgroups per client as stay resident, <= 16
-            f->W = (int)std::max<int64_t>(1, std::min<int64_t>(16, resident / K));
+            // automatic: as many workgroups per client as stay resident, but
+            // no more than leave each wavefront about four 64-sample chunks
+            // of a local step (beyond that the extra workgroups only add
+            // barrier arrivals and LDS flushes)
+            const int64_t busy = ceil_div(ceil_div(D.p + D.q, 64), 4 * (int64_t)(f->block / 64));
+            f->W = (int)std::max<int64_t>(1, std::min<int64_t>(busy, resident / K));
             reinterpret_cast<FedArgs<T>*>(f->args)->W = f->W;
         }
         if ((int64_t)K * f->W > resident)
@@ -856,15 +860,8 @@ gcp_status gcp_fedadam_create(gcp_fed* out, const gcp_fed_desc* desc, hipStream_
         delete f;
         return set_error(GCP_ERR_ARG, "lane shape %d x %d does not cover R = %d", f->lanes, f->vec, D.R);
     }
-    if (D.batched) {
-        if (D.workgroups_per_client > 0) f->W = D.workgroups_per_client;
-        else {
-            // fill the GPU with resident workgroups, at most 16 per client
-            const int cus = device_cu_count(f->device);
-            const int per_cu = std::max(1, 2048 / f->block);     // waves per CU budget of 32
-            f->W = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)cus * per_cu / 2 / D.nclients));
-        }
-    }
+    // the automatic count is set once the kernel is chosen (its occupancy)
+    if (D.batched) f->W = D.workgroups_per_client > 0 ? D.workgroups_per_client : 1;
     (void)esize;
     gcp_status st = f->dt == GCP_F32 ? fed_build<float>(f) : fed_build<double>(f);
     if (st != GCP_OK) {

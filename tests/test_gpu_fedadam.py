@@ -334,7 +334,8 @@ def test_fp32_four_way_rounds_match_oracle(gpu, scatter):
     blocks = _blocks(gdims, (2, 2, 1, 2), R, 200, 900, seed=2616)
     U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2716, dtype=torch.float64)
     cfg = FedConfig(R=R, tau=2, loss="poisson", p=600, q=500, seed=8, lr=1e-3, meta_lr=1e-3, lower=0.0)
-    tile = FedTile() if scatter == "atomic" else FedTile(lds_modes=0, bucket_modes=15, bucket_block_samples=512)
+    tile = (FedTile(workgroups_per_client=3) if scatter == "atomic" else
+            FedTile(lds_modes=0, bucket_modes=15, bucket_block_samples=512))
     say(f"fedadam fp32 4-way {scatter}")
     fed = FedAdam(_gpu_clients(blocks, torch.float32, gpu), gdims, U0.to(torch.float32).to(gpu), cfg, tile=tile)
     assert fed.info()["form"] == ("persistent" if scatter == "atomic" else "row_bucketed")
@@ -358,7 +359,7 @@ def test_fp32_two_and_five_way_rounds_match_oracle(gpu, gdims, grid, scatter):
     U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2718 + d, dtype=torch.float64)
     cfg = FedConfig(R=R, tau=2, loss="poisson", p=300, q=200, seed=9, lr=1e-3, meta_lr=1e-3, lower=0.0)
     full = (1 << d) - 1
-    tile = {"atomic": FedTile(),
+    tile = {"atomic": FedTile(workgroups_per_client=3),
             "bucketed": FedTile(lds_modes=0, bucket_modes=full, bucket_block_samples=512),
             "lds_and_bucketed": FedTile(lds_modes=1, bucket_modes=full & ~1, bucket_block_samples=512)}[scatter]
     say(f"fedadam fp32 {d}-way {scatter}")
@@ -418,6 +419,30 @@ def test_wide_rank_rounds_match_oracle(gpu, dtype, R, scatter):
     fed.status()
     Uo, ocl = _run_oracle(blocks, gdims, R, U0.to(dtype), cfg, 2, dtype)
     _assert_state_matches(fed, Uo, ocl, 1e-10 if dtype == torch.float64 else FP32_TOL, f"R={R} {scatter}")
+
+
+def test_automatic_workgroups_per_client(gpu):
+    """The persistent launch's automatic workgroups per client: one for a
+    local step of two 64-sample chunks; for 128 chunks at 256 threads (four
+    wavefronts) enough for four chunks per wavefront, 8, which the GPU holds
+    for 8 clients -- and that round matches the oracle."""
+    gdims, R = SMALL["gdims"], SMALL["R"]
+    blocks = _blocks(gdims, SMALL["grid"], R, SMALL["nmin"], SMALL["nmax"], seed=2620)
+    U0 = 0.2 + 0.8 * synth.init_model(gdims, R, 2720, dtype=torch.float64)
+    for pq, want in ((64, 1), (4096, 8)):
+        cfg = FedConfig(R=R, tau=2, loss="poisson", p=pq, q=pq, seed=12, lr=1e-2, meta_lr=1e-2, lower=0.0)
+        fed = FedAdam(_gpu_clients(blocks, torch.float64, gpu), gdims, U0.to(gpu), cfg, tile=FedTile(bucket_modes=0))
+        info = fed.info()
+        assert info["form"] == "persistent" and info["block"] == 256, info
+        assert info["workgroups_per_client"] == want, (pq, info)
+        if pq == 4096:
+            fed.round(0)
+            fed.status()
+            Uo, ocl = _run_oracle(blocks, gdims, R, U0, cfg, 1, torch.float64)
+            assert _rel(fed.U.cpu().numpy(), Uo) <= 1e-10
+            for cl, oc in zip(fed.clients, ocl):
+                assert _rel(cl.B.cpu().numpy(), oc.B) <= 1e-10
+        fed.close()
 
 
 def test_batched_and_plain_classes_equal_the_flags(gpu):

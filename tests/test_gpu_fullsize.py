@@ -4,9 +4,11 @@ times.
 10000 x 8000 x 6000 Poisson tensor with 5e7 nonzeros, rank 32, 2^20 + 2^20
 stratified samples: every one of the 2^21 samples is checked bit for bit
 against the oracle's own draw (its sorted-tuple binary search against the
-GPU's hash table), and the whole gradient of the fused kernel -- atomic and
-row-bucketed scatter -- against the oracle's gradient on its own samples,
-element by element within the float32 rounding bound.
+GPU's hash table), and the whole gradient of the fused kernel -- atomic,
+row-bucketed (the automatic choice, and the exact launch shape the benchmark
+times, read from the traffic summary it pairs its timing with) and
+bit-reproducible -- against the oracle's gradient on its own samples, element
+by element within the float32 rounding bound.
 
 GCP-FedAdam, 64 clients on a 4 x 4 x 4 grid over 20000 x 20000 x 2000 with
 1e5..5e6 nonzeros per client: one batched (graph-replayed) round, with the
@@ -14,6 +16,8 @@ automatic (row-bucketed at this size) and with the atomic scatter, and one
 per-client round with each call's automatic scatter, equal one round of
 per-client launches with hardware atomics (U, every M_c and every B_c).
 """
+import json
+import os
 import sys
 import time
 
@@ -46,6 +50,10 @@ def test_config2_full_size_samples_and_gradient(gpu):
     c, x, w = G.gcp_sample(t, sp)
     Ga, La = G.gcp_loss_grad(t, sp, A, R, "poisson", tile=G.Tile(bucket_modes=0, lds_modes=0))
     Gb, Lb = G.gcp_loss_grad(t, sp, A, R, "poisson")                     # automatic: row-bucketed
+    # the benchmark's launch shape: the tile of its traffic summary
+    with open(os.path.join(os.path.dirname(__file__), "..", "profiles", "loss_grad_cfg2_traffic.json")) as f:
+        bench_tile = G.Tile(**json.load(f)["tile"])
+    Gt, Lt = G.gcp_loss_grad(t, sp, A, R, "poisson", tile=bench_tile)
     Gd, Ld = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
     Gd2, Ld2 = G.gcp_loss_grad(t, sp, A, R, "poisson", deterministic=True)
     t.status()
@@ -64,7 +72,8 @@ def test_config2_full_size_samples_and_gradient(gpu):
     say(f"config 2: oracle gradient at {time.time() - t0:.1f} s")
     Go = Go.reshape(-1, R)
     A64 = A.double().cpu().numpy().reshape(-1)
-    for name, (Gx, Lx) in (("atomic", (Ga, La)), ("bucketed", (Gb, Lb)), ("deterministic", (Gd, Ld))):
+    for name, (Gx, Lx) in (("atomic", (Ga, La)), ("bucketed", (Gb, Lb)), (f"benchmark tile {bench_tile}", (Gt, Lt)),
+                           ("deterministic", (Gd, Ld))):
         # every element within the rounding bound of float32 arithmetic in
         # any summation order, and per mode within 1e-5 relative
         frob, worst = assert_grad_close(Gx.cpu().numpy(), Go, dims, R, A64, oc, ox, ow, "poisson", torch.float32,
