@@ -255,7 +255,7 @@ def run_fedadam(dev, rounds: int, tune: bool = True, workload: str = "3way"):
         fed = FedAdam(clients, gd, U0, cfg, batched=True, use_graph=True,
                       tile=FedTile(bucket_modes=0) if name == "persistent" else FedTile())
         if tune:
-            pool = [c for c in autotune.fed_candidates(R, torch.float32, len(clients))
+            pool = [c for c in autotune.fed_candidates(R, torch.float32, len(clients), nmodes=len(gd))
                     if (c.bucket_modes == 0) == (cands == "persistent")]
             autotune.tune_fedadam(fed, candidates=pool, rounds=1, warmup=1, use_cache=False)
         measure(name, fed)

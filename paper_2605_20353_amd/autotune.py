@@ -64,15 +64,16 @@ def _time(fn, stream, reps: int, warmup: int) -> float:
 def fed_candidates(R: int, dtype, nclients: int, cus: int = 256, nmodes: int = 3):
     """Launch shapes worth trying for a batched round: the persistent launch
     with the atomic scatter over lane shapes, workgroup sizes and workgroups
-    per client, then the row-bucketed rounds (three launches per local step)
-    over lane shapes (0 = its default) and workgroup sizes."""
+    per client (0 = the library's automatic count), then the row-bucketed
+    rounds (three launches per local step) over lane shapes (0 = its default)
+    and workgroup sizes."""
     shapes = [(32, 1), (16, 2)] if R == 32 else [(0, 0)]
     if dtype == torch.float32 and R == 32:
         shapes.append((8, 4))
     out = []
     for block in (256, 512):
         max_w = max(1, (cus * (2048 // block)) // (2 * nclients))
-        for w in sorted({1, 2, 4, 8, 16, max_w}):
+        for w in sorted({0, 1, 2, 4, 8, 16, max_w}):
             if w > max_w:
                 continue
             for lanes, vec in shapes:
