@@ -789,6 +789,14 @@ def main():
         extras["deterministic_call_ms"] = _median_ms(
             lambda: G.gcp_loss_grad(t, sp0, A, RANK, "poisson", G=Gd, want_loss=False, deterministic=True), 10, 2)
         log(f"deterministic call {extras['deterministic_call_ms']:.3f} ms")
+        # semi-stratified sampling (zero samples kept without a membership
+        # search) against stratified, same tile and timing method
+        sps = G.SampleParams("semi_stratified", P, Q, seed=SAMPLE_SEED, step=0)
+        for name, spx in (("stratified", sp0), ("semi_stratified", sps)):
+            extras[f"{name}_call_ms"] = _median_ms(
+                lambda: G.gcp_loss_grad(t, spx, A, RANK, "poisson", G=Gd, want_loss=False, tile=tile), 20, 3)
+        log(f"stratified call {extras['stratified_call_ms']:.3f} ms, semi-stratified "
+            f"{extras['semi_stratified_call_ms']:.3f} ms (host-synchronised timing)")
         del Gd
     cpu = None
     if not args.no_cpu_baseline:
