@@ -159,7 +159,8 @@ typedef struct gcp_tile {
                                    the objective's per-wavefront partial sums
                                    are added in a fixed order.  Drawn samples
                                    only (smp must be NULL); needs the workspace
-                                   of gcp_tensor_reserve; slower than the
+                                   of gcp_tensor_reserve and (p + q) d < 2^32
+                                   (GCP_ERR_ARG otherwise); slower than the
                                    default scatter                             */
 /* gcp_adam_step flags */
 #define GCP_ADAM_ZERO_GRAD 1u   /* write G = 0 after reading it                */

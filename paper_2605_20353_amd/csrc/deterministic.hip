@@ -223,9 +223,13 @@ gcp_status launch_det(gcp_tensor_s* t, const gcp_sample_params* sp, const void* 
     if (!G_out) return set_error(GCP_ERR_ARG, "G_out is NULL");
     if ((flags & GCP_SCALE_BY_DEV) && !scale_dev) return set_error(GCP_ERR_ARG, "scale_dev is NULL");
     const int64_t n = sp->p + sp->q;
-    if (n < 0 || n > t->ws_max_samples || n >= (int64_t(1) << 32))
+    if (n < 0 || n > t->ws_max_samples)
         return set_error(GCP_ERR_ARG, "GCP_DETERMINISTIC: %lld samples exceed the reserved %lld",
                          (long long)n, (long long)t->ws_max_samples);
+    // (row, sample) pairs are indexed with 32 bits (run starts, sorted values)
+    if (n * t->d >= (int64_t(1) << 32))
+        return set_error(GCP_ERR_ARG, "GCP_DETERMINISTIC: %lld samples x %d modes reach 2^32 (row, sample) pairs",
+                         (long long)n, t->d);
     DetLayout L{};
     gcp_status st = det_layout(t, n, L);
     if (st != GCP_OK) return st;
