@@ -620,61 +620,62 @@ __device__ __forceinline__ void bucket_accumulate(const LGParams<T>& P, int k, i
         __syncthreads();
         return;
     }
+    // General order (run-time d, either key form), with the loads as
+    // unconditional as above: the d - 1 modes other than k fill slots
+    // 0 .. d - 2 in mode order (slot o holds mode o, or o + 1 from k on, both
+    // compile-time indices), slots past d - 2 re-read column block 0 of the
+    // first model row and count as ones, lanes past column R read column 0,
+    // and lanes past the segment's end re-read its last entry.
+    constexpr int SO = DM - 1;
+    const int colL = col_ok ? col0 : 0;
     for (int64_t j = j0 + wave; j < j1; j += nwaves) {
         const int cnt = seg_cnt[j - j0];
+        if (cnt == 0) continue;
         const uint4* seg = P.entries + j * P.entry_cap + seg_start[j - j0];
         // entries of the next pass are loaded while this pass gathers rows
         uint4 nxt[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = u * S + g;
-            nxt[u] = e < cnt ? seg[e] : make_uint4(0, 0, 0, 0);
-        }
+        for (int u = 0; u < U; ++u) nxt[u] = seg[min(u * S + g, cnt - 1)];
         for (int base = 0; base < cnt; base += S * U) {
             uint32_t ik[U];
             T y[U];
-            T a[U][DM][VEC];
+            T a[U][SO][VEC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int e = base + u * S + g;
-                const bool valid = e < cnt;
                 const uint4 ent = nxt[u];
-                const int en = e + S * U;
-                nxt[u] = en < cnt ? seg[en] : make_uint4(0, 0, 0, 0);
                 const uint64_t key = (uint64_t)ent.x | ((uint64_t)ent.y << 32);
                 uint32_t ci[DM];
-                unpack_all<D == 0>(P.sc.L, dd, key, ci);
+                unpack_all<true>(P.sc.L, dd, key, ci);
                 // the owned mode's row, picked with compile-time indices
                 ik[u] = ci[0];
 #pragma unroll
                 for (int kk = 1; kk < DM; ++kk)
                     if (kk == k) ik[u] = ci[kk];
-                y[u] = valid ? entry_y<T>(ent) : T(0);
+                y[u] = entry_y<T>(ent);
 #pragma unroll
-                for (int kk = 0; kk < DM; ++kk) {
-                    if (kk < dd) {
-                        if (kk != k && col_ok && valid) {
-                            const uint64_t row = (uint64_t)P.rowoff[kk] + ci[kk];
-                            load_cols<T, VEC>(P.A + row_elem(row, R) + col0, a[u][kk]);
-                        } else {
-#pragma unroll
-                            for (int v = 0; v < VEC; ++v) a[u][kk][v] = T(1);
-                        }
-                    }
+                for (int o = 0; o < SO; ++o) {
+                    const bool after = o >= k;
+                    const uint64_t row = after ? (uint64_t)P.rowoff[o + 1] + ci[o + 1] : (uint64_t)P.rowoff[o] + ci[o];
+                    const T* src = P.A + (o < dd - 1 ? row_elem(row, R) : 0) + colL;
+                    load_cols<T, VEC>(src, a[u][o]);
                 }
             }
+            // the next pass's entries stay in flight through this pass's
+            // scatter
+#pragma unroll
+            for (int u = 0; u < U; ++u) nxt[u] = seg[min(base + S * U + u * S + g, cnt - 1)];
+            __asm__ volatile("" ::: "memory");
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int e = base + u * S + g;
-                if (e >= cnt || !col_ok) continue;
+                if (base + u * S + g >= cnt || !col_ok) continue;
                 const uint32_t i = ik[u] - (uint32_t)r0;
                 T c[VEC];
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
                     c[v] = y[u];
 #pragma unroll
-                    for (int kk = 0; kk < DM; ++kk)
-                        if (kk < dd) c[v] *= a[u][kk][v];
+                    for (int o = 0; o < SO; ++o)
+                        if (o < dd - 1) c[v] *= a[u][o][v];
                 }
                 lds_add_cols<T, VEC>(part + i * (uint32_t)R + col0, c);
             }
