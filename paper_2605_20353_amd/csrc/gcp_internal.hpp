@@ -220,20 +220,6 @@ __host__ __device__ __forceinline__ void unpack_all(const KeyLayout& L, int dd, 
     }
 }
 
-// Coordinate of mode k (k may vary at run time) of a key.
-template <bool RADIX, int DM>
-__host__ __device__ __forceinline__ uint32_t unpack_one(const KeyLayout& L, int dd, uint64_t key, int k)
-{
-    if (!RADIX || !L.radix) return (uint32_t)((key >> L.shift[k]) & L.mask[k]);
-    uint32_t c[DM];
-    unpack_all<true>(L, dd, key, c);
-    uint32_t r = c[0];
-#pragma unroll
-    for (int j = 1; j < DM; ++j)
-        if (j == k) r = c[j];
-    return r;
-}
-
 // Candidate cell of sample s / attempt a drawn straight into a cell key.
 template <int D>
 __device__ __forceinline__ uint64_t draw_cell_key(const KeyLayout& L, int d, uint64_t seed, uint64_t client,
