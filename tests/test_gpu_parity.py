@@ -43,6 +43,7 @@ CASES = {
     "8way": ([3, 4, 2, 5, 3, 2, 4, 3], 500, 4),          # the most modes a tensor may have
     "r1_unit_mode": ([40, 1, 30], 300, 1),              # rank 1, and a mode of one index (no key bits)
     "5way_r33": ([6, 5, 4, 3, 7], 200, 33),             # general order, odd rank: 64 lanes of one column
+    "2way": ([50, 40], 600, 6),                         # matrix: general-order kernels, 30% dense
 }
 
 
@@ -351,6 +352,32 @@ def test_bucketed_scatter_matches_oracle(gpu, dtype, loss, pq):
     Gs, _ = G.gcp_loss_grad(t_gpu, sp, A, R, loss, G=Gs, accumulate=True, scale=scale,
                             tile=G.Tile(bucket_modes=7, lds_modes=0))
     ref.check(Gs, dtype, "scaled and accumulated", bound_scale=2.0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", ["1way", "2way", "5way", "8way", "5way_r33"])
+def test_bucketed_scatter_general_order(gpu, dtype, name):
+    """The general-order owner pass (the modes other than the owned one in
+    compile-time slots, unused slots multiplying as ones): orders 1, 2, 5 and
+    8, and an odd rank, every mode row-bucketed or mixed with LDS-private
+    modes, several sorted blocks with ragged ends, against the oracle."""
+    t_gpu, t_ora, dims, R = make_case(name, dtype, gpu)
+    d = len(dims)
+    full = (1 << d) - 1
+    sp = G.SampleParams("stratified", 1300, 901, seed=37, step=3)
+    t_gpu.reserve(sp.n, R)
+    A = model(dims, R, dtype, gpu)
+    ref = oracle_ref(t_ora, dims, R, A, "poisson", sp)
+    tiles = [dict(bucket_modes=full, lds_modes=0, bucket_block_samples=512),
+             dict(bucket_modes=full, lds_modes=0, bucket_block_samples=1024, bucket_splits=3, bucket_block=64)]
+    if d > 1:
+        tiles.append(dict(bucket_modes=full & ~1, lds_modes=1, bucket_block_samples=512))
+    for tl in tiles:
+        say(f"bucketed general order {name} {dtype} {tl}")
+        Gg, Lg = G.gcp_loss_grad(t_gpu, sp, A, R, "poisson", tile=G.Tile(**tl))
+        t_gpu.status()
+        ref.check(Gg, dtype, tl)
+        ref.check_loss(Lg, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
